@@ -1,0 +1,136 @@
+/*
+ * mcm.h -- C ABI of the gfx950 matrix-chain-multiplication DP solver.
+ *
+ * The operation (Section IV of the paper, "Solving MCM Problem"; the paper
+ * takes the cost function from the textbook MCM definition): for a chain of
+ * n matrices where matrix t (0-based) has p[t] rows and p[t+1] columns,
+ * fill the triangular solution table along the diagonal direction (Fig. 5),
+ * each element being the minimum over its splits of a function of the left
+ * and right sub-results (Fig. 6, Eq. (2)):
+ *
+ *   m[i][i] = 0
+ *   m[i][j] = min_{i <= k < j} m[i][k] + m[k+1][j] + p[i]*p[k+1]*p[j+1]
+ *   s[i][j] = the smallest k attaining the minimum              (i < j)
+ *
+ * Output contract (every byte of both buffers is written):
+ *   m_out: int64, n*n, row-major, symmetric: m_out[i*n+j] = m_out[j*n+i] =
+ *          the optimal cost of matrices min(i,j)..max(i,j); zero diagonal.
+ *   s_out: int32, n*n, row-major: s_out[i*n+j] = 0-based split k (the
+ *          product is (A_i..A_k)(A_k+1..A_j)) for i < j, and -1 for i >= j.
+ * Results are exact integers and deterministic; every algorithm below
+ * returns the same bytes.
+ *
+ * Preconditions checked on the host before anything is enqueued (on error
+ * nothing is enqueued and the output buffers are not touched):
+ *   n >= 1, every p[t] >= 1, and (n-1) * max(p)^3 < 2^63 (every candidate
+ *   cost of cell (i, j) is at most (j-i) * max(p)^3, so int64 is exact).
+ *
+ * Threading and streams: calls are thread-safe.  Work is enqueued on
+ * `stream` (0 = the null stream) and the call returns without waiting for
+ * it; the caller synchronises the stream before reading the outputs.  The
+ * library reads the host array p before returning, so the caller may reuse
+ * it immediately.  Workspace is allocated stream-ordered on `stream` and
+ * released on it.  Outputs of concurrent calls must not alias.
+ *
+ * Errors: MCM_ERR_INVALID_ARG / MCM_ERR_OVERFLOW for bad inputs (synchronous,
+ * nothing enqueued); MCM_ERR_NO_MEMORY when workspace allocation fails;
+ * MCM_ERR_DEVICE when the HIP runtime reports an error while enqueueing
+ * (including errors left by earlier asynchronous work).
+ */
+#ifndef MCM_H_
+#define MCM_H_
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mcm_status {
+    MCM_OK = 0,
+    MCM_ERR_INVALID_ARG = 1,
+    MCM_ERR_OVERFLOW = 2,
+    MCM_ERR_NO_MEMORY = 3,
+    MCM_ERR_DEVICE = 4,
+    MCM_ERR_UNSUPPORTED = 5
+} mcm_status;
+
+/*
+ * Kernel paths.  All produce identical bytes; they differ in speed and in
+ * the inputs they accept.
+ *   MCM_ALGO_AUTO       pick the fastest path that accepts the input.
+ *   MCM_ALGO_WAVEFRONT  one launch per diagonal of the table; every cell of
+ *                       a diagonal is independent (Fig. 5 order), its splits
+ *                       are scanned by a group of lanes and reduced in
+ *                       registers.  int64 arithmetic; accepts every valid
+ *                       input.
+ *   MCM_ALGO_TILED      T x T tiles of the table in tile-diagonal order;
+ *                       operand panels staged through LDS and reused across
+ *                       a register microtile; split range spread over
+ *                       workgroups; a per-tile closure pass in LDS.  Exact
+ *                       integers carried in fp64; accepts inputs with
+ *                       (n-1) * max(p)^3 < 2^44 (else MCM_ERR_UNSUPPORTED).
+ */
+typedef enum mcm_algo {
+    MCM_ALGO_AUTO = 0,
+    MCM_ALGO_WAVEFRONT = 1,
+    MCM_ALGO_TILED = 2
+} mcm_algo;
+
+/* Static, NUL-terminated description of a status code (never NULL). */
+const char *mcm_status_string(int32_t status);
+
+/* ABI version: major * 10000 + minor * 100 + patch. */
+int32_t mcm_version(void);
+
+/*
+ * Host-only validation of a chain (no device call): MCM_OK,
+ * MCM_ERR_INVALID_ARG (p == NULL, n < 1, or some p[t] < 1) or
+ * MCM_ERR_OVERFLOW ((n-1) * max(p)^3 >= 2^63).  p: host, n+1 entries.
+ */
+mcm_status mcm_check_chain(const int32_t *p, int32_t n);
+
+/*
+ * The algorithm MCM_ALGO_AUTO would use for this chain (host only), or a
+ * negative status code (-MCM_ERR_*) if the chain is invalid.
+ */
+int32_t mcm_select_algo(const int32_t *p, int32_t n);
+
+/*
+ * Fill m_out and s_out for one chain (the operation above).
+ *   p      host pointer, n+1 dimensions (read before return).
+ *   n      number of matrices, >= 1.
+ *   m_out  device pointer, n*n int64, 8-byte aligned, caller-owned.
+ *   s_out  device pointer, n*n int32, 4-byte aligned, caller-owned.
+ *   stream HIP stream, or 0.
+ * Equivalent to mcm_solve_algo(..., MCM_ALGO_AUTO, stream).
+ */
+mcm_status mcm_solve(const int32_t *p, int32_t n, int64_t *m_out, int32_t *s_out,
+                     hipStream_t stream);
+
+/* mcm_solve with an explicit kernel path (mcm_algo).  MCM_ERR_UNSUPPORTED
+ * if that path does not accept the input; MCM_ERR_INVALID_ARG for an
+ * unknown algo. */
+mcm_status mcm_solve_algo(const int32_t *p, int32_t n, int64_t *m_out, int32_t *s_out,
+                          int32_t algo, hipStream_t stream);
+
+/*
+ * Kernel-level profiling on the library's own launches (HIP events on the
+ * stream each kernel is enqueued on).  Enabling clears the counters;
+ * reading synchronises the recorded events.  Classes:
+ *   0 setup (diagonal tiles / init), 1 tiled bulk, 2 tiled closure,
+ *   3 wavefront diagonals, 4 batched.
+ * mcm_profile_read returns MCM_OK and fills: total kernel milliseconds,
+ * number of launches, and the split evaluations those launches performed
+ * (the algorithmic count, not counting padding).
+ */
+void mcm_profile_enable(int32_t on);
+mcm_status mcm_profile_read(int32_t kernel_class, double *total_ms, int64_t *launches,
+                            double *split_evals);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCM_H_ */

@@ -1,0 +1,176 @@
+"""ctypes binding of ``libmcm.so`` (argument marshalling only).
+
+Every step of the solve runs in the library's HIP kernels; this module only
+converts arguments.  PyTorch supplies device memory and the stream.  If the
+library has not been built, every call raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+from .build import LIB
+
+OK = 0
+ERR_INVALID_ARG = 1
+ERR_OVERFLOW = 2
+ERR_NO_MEMORY = 3
+ERR_DEVICE = 4
+ERR_UNSUPPORTED = 5
+
+ALGO_AUTO = 0
+ALGO_WAVEFRONT = 1
+ALGO_TILED = 2
+ALGOS = {"auto": ALGO_AUTO, "wavefront": ALGO_WAVEFRONT, "tiled": ALGO_TILED}
+
+# Profiler kernel classes (mcm_profile_read).
+PROF_SETUP, PROF_BULK, PROF_CLOSE, PROF_WAVE, PROF_BATCH = range(5)
+
+# Every symbol include/mcm.h declares.
+EXPORTED = (
+    "mcm_status_string", "mcm_version", "mcm_check_chain", "mcm_select_algo",
+    "mcm_solve", "mcm_solve_algo", "mcm_profile_enable", "mcm_profile_read",
+)
+
+
+class MCMError(RuntimeError):
+    """A non-zero mcm_status from the library."""
+
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} (status {status})")
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib_path() -> str:
+    return LIB
+
+
+def load() -> ctypes.CDLL:
+    """Load the built library (raises if it is missing)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB):
+                raise RuntimeError(
+                    f"{LIB} is not built; run `python -m paper_2008_01938_amd.build` "
+                    "(or __graft_entry__.build())")
+            lib = ctypes.CDLL(LIB)
+            i32p = ctypes.POINTER(ctypes.c_int32)
+            vp = ctypes.c_void_p
+            lib.mcm_status_string.argtypes = [ctypes.c_int32]
+            lib.mcm_status_string.restype = ctypes.c_char_p
+            lib.mcm_version.argtypes = []
+            lib.mcm_version.restype = ctypes.c_int32
+            lib.mcm_check_chain.argtypes = [i32p, ctypes.c_int32]
+            lib.mcm_check_chain.restype = ctypes.c_int
+            lib.mcm_select_algo.argtypes = [i32p, ctypes.c_int32]
+            lib.mcm_select_algo.restype = ctypes.c_int32
+            lib.mcm_solve.argtypes = [i32p, ctypes.c_int32, vp, vp, vp]
+            lib.mcm_solve.restype = ctypes.c_int
+            lib.mcm_solve_algo.argtypes = [i32p, ctypes.c_int32, vp, vp, ctypes.c_int32, vp]
+            lib.mcm_solve_algo.restype = ctypes.c_int
+            lib.mcm_profile_enable.argtypes = [ctypes.c_int32]
+            lib.mcm_profile_enable.restype = None
+            lib.mcm_profile_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(ctypes.c_double)]
+            lib.mcm_profile_read.restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return load().mcm_status_string(int(status)).decode()
+
+
+def version() -> int:
+    return int(load().mcm_version())
+
+
+def _dims(p) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(p, dtype=np.int32))
+    if a.ndim != 1:
+        raise ValueError("p must be one-dimensional")
+    return a
+
+
+def _p_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def check_chain(p) -> int:
+    """mcm_check_chain status for p[0..n] (host only)."""
+    a = _dims(p)
+    return int(load().mcm_check_chain(_p_ptr(a), a.size - 1))
+
+
+def select_algo(p) -> int:
+    a = _dims(p)
+    return int(load().mcm_select_algo(_p_ptr(a), a.size - 1))
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def solve_into(p, m, s, algo: int | str = ALGO_AUTO, stream=None) -> None:
+    """Enqueue the solve of chain p into preallocated device tensors.
+
+    m: int64 CUDA tensor with n*n elements, s: int32 CUDA tensor with n*n
+    elements (both contiguous).  Returns once enqueued on `stream`
+    (default: torch's current stream).
+    """
+    import torch
+    a = _dims(p)
+    n = a.size - 1
+    if isinstance(algo, str):
+        algo = ALGOS[algo]
+    if not (m.is_cuda and s.is_cuda and m.dtype == torch.int64 and s.dtype == torch.int32):
+        raise TypeError("m must be a CUDA int64 tensor and s a CUDA int32 tensor")
+    if not (m.is_contiguous() and s.is_contiguous()) or m.numel() < n * n or s.numel() < n * n:
+        raise ValueError("m and s must be contiguous with at least n*n elements")
+    st = load().mcm_solve_algo(_p_ptr(a), n, ctypes.c_void_p(m.data_ptr()),
+                               ctypes.c_void_p(s.data_ptr()), int(algo),
+                               ctypes.c_void_p(_stream_handle(stream)))
+    if st != OK:
+        raise MCMError(st, "mcm_solve_algo")
+
+
+def solve(p, algo: int | str = ALGO_AUTO, device="cuda", stream=None):
+    """Solve chain p; returns (m, s) as (n, n) CUDA tensors (int64, int32).
+
+    The work is enqueued on `stream`; synchronise before reading on the host.
+    """
+    import torch
+    a = _dims(p)
+    n = a.size - 1
+    m = torch.empty((max(n, 0), max(n, 0)), dtype=torch.int64, device=device)
+    s = torch.empty((max(n, 0), max(n, 0)), dtype=torch.int32, device=device)
+    solve_into(a, m, s, algo=algo, stream=stream)
+    return m, s
+
+
+def profile_enable(on: bool = True) -> None:
+    load().mcm_profile_enable(1 if on else 0)
+
+
+def profile_read(kernel_class: int) -> dict:
+    """{'ms', 'launches', 'split_evals'} accumulated for a kernel class."""
+    ms = ctypes.c_double(0.0)
+    nl = ctypes.c_int64(0)
+    ev = ctypes.c_double(0.0)
+    st = load().mcm_profile_read(int(kernel_class), ctypes.byref(ms), ctypes.byref(nl),
+                                 ctypes.byref(ev))
+    if st != OK:
+        raise MCMError(st, "mcm_profile_read")
+    return {"ms": ms.value, "launches": nl.value, "split_evals": ev.value}

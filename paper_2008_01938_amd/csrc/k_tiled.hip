@@ -1,0 +1,443 @@
+// Tiled MCM table fill for gfx950.
+//
+// The table is cut into T x T tiles; tile (I, J), I <= J, holds cells
+// i in [I*T, I*T+T), j in [J*T, J*T+T).  Tiles are processed in
+// tile-diagonal order D = J - I, the block analogue of the diagonal order
+// of the paper's Fig. 5.  For an off-diagonal tile the splits k of a cell
+// fall into three ranges:
+//
+//   (a) k in [i, (I+1)T-2]     left operand in diagonal tile (I,I),
+//                              right operand in the tile itself (below);
+//   bulk k in [(I+1)T-1, JT-1] both operands in tiles of earlier
+//                              tile-diagonals -- the same range for every
+//                              cell of the tile;
+//   (b) k in [JT, j-1]         left operand in the tile itself (to the
+//                              left), right operand in diagonal tile (J,J).
+//
+// k_tri fills the diagonal tiles (all their splits stay inside the tile).
+// k_bulk evaluates the bulk range of every tile of one tile-diagonal: a
+// min-plus-like reduction where the A panel (rows of I, columns k) and the
+// B panel (rows k+1, columns of J) are staged through LDS and each thread
+// keeps a 4 x 4 register microtile of running minima.  The bulk range is
+// cut into chunks spread over workgroups; each writes packed (cost, k)
+// partial minima.  k_close merges the partials and then adds the (a) and
+// (b) splits, which depend on cells of the same tile: cell (r, c) (local
+// row/column) needs the cells below it in its column and left of it in its
+// row, so the tile is swept in local anti-diagonals w = (T-1-r) + c, one
+// workgroup barrier per anti-diagonal, entirely in LDS.
+//
+// Exact integers in fp64.  A candidate cost of cell (i, j) is at most
+// (j-i) * pmax^3 < 2^cost_bits.  The kernels carry
+// key = cost * 2^kb + k_local as a double with kb = 53 - cost_bits, so
+// every key, and every partial sum that forms it (all integers), is below
+// 2^53 and therefore exact; one fp64 min then picks the smallest cost and,
+// among equal costs, the smallest k_local -- the smallest k when k_local
+// increases with k.  A split evaluation is fma + add + min.
+#include <math.h>
+
+#include "mcm_internal.h"
+
+namespace mcm {
+namespace {
+
+constexpr int T = 64;        // tile edge
+constexpr int KC = 16;       // k values staged per LDS round in k_bulk
+constexpr int NTH = 256;     // threads per workgroup
+constexpr double kPad = 4611686018427387904.0;  // 2^62: never wins a min
+
+// ------------------------------------------------------------------------
+// Diagonal tiles (I, I): every split of a cell inside the tile uses two
+// cells of the same tile.  Local diagonals dd = 1..nI-1 in order; four
+// lanes per cell, lexicographic (cost, k) reduction.  int64 arithmetic.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(NTH) void k_tri(const int32_t *__restrict__ p, int32_t n,
+                                             int64_t *__restrict__ m, int32_t *__restrict__ s)
+{
+    __shared__ int64_t tv[T][T + 1];
+    __shared__ int32_t sv[T][T + 1];
+    __shared__ int64_t ps[T + 1];
+    const int tid = threadIdx.x;
+    const int base = blockIdx.x * T;
+    const int nI = min(T, n - base);
+    for (int q = tid; q <= nI; q += NTH) ps[q] = p[base + q];
+    for (int r = tid; r < T; r += NTH) tv[r][r] = 0;
+    __syncthreads();
+
+    const int r = tid >> 2, g = tid & 3;
+    for (int dd = 1; dd < nI; ++dd) {
+        const int c = r + dd;
+        int64_t best = INT64_MAX;
+        int32_t arg = INT32_MAX;
+        if (c < nI) {
+            const int64_t prc = ps[r] * ps[c + 1];
+            for (int kl = r + g; kl < c; kl += 4) {
+                const int64_t v = tv[r][kl] + tv[kl + 1][c] + prc * ps[kl + 1];
+                if (v < best) {
+                    best = v;
+                    arg = kl;
+                }
+            }
+        }
+#pragma unroll
+        for (int off = 1; off < 4; off <<= 1) {
+            const int64_t ov = __shfl_xor(best, off, 4);
+            const int32_t oa = __shfl_xor(arg, off, 4);
+            if (ov < best || (ov == best && oa < arg)) {
+                best = ov;
+                arg = oa;
+            }
+        }
+        if (c < nI && g == 0) {
+            tv[r][c] = best;
+            sv[r][c] = base + arg;
+        }
+        __syncthreads();
+    }
+
+    for (int idx = tid; idx < T * T; idx += NTH) {
+        const int rr = idx / T, cc = idx % T;
+        if (rr < nI && cc < nI) {
+            const size_t o = (size_t)(base + rr) * n + base + cc;
+            m[o] = rr <= cc ? tv[rr][cc] : tv[cc][rr];
+            s[o] = rr < cc ? sv[rr][cc] : -1;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Bulk splits of tile-diagonal D >= 2.  Workgroup b handles tile I = b / P
+// (J = I + D) and chunk b % P of its bulk range.  Thread (tx, ty) owns the
+// cells rows ty + 16a, columns tx + 16b (a, b = 0..3) of the tile.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(NTH) void k_bulk(const int64_t *__restrict__ m,
+                                              const double *__restrict__ pd, int32_t n,
+                                              int32_t D, int32_t KS, int32_t P, int32_t kb,
+                                              int32_t kbits, uint64_t *__restrict__ part)
+{
+    __shared__ double As[2][KC][T + 1];  // As[kk][r] = m[row0+r][k] * 2^kb
+    __shared__ double Bs[2][KC][T];      // Bs[kk][c] = m[k+1][col0+c] * 2^kb + (k - k0)
+    __shared__ double Ps[2][KC];         // p[k+1]
+
+    const int tid = threadIdx.x;
+    const int tile = blockIdx.x / P;
+    const int chunk = blockIdx.x - tile * P;
+    const int I = tile, J = tile + D;
+    const int row0 = I * T, col0 = J * T;
+    const int k0 = (I + 1) * T - 1 + chunk * KS;
+    const int kend = min(k0 + KS, col0);  // exclusive end of this chunk
+    const int nJ = min(T, n - col0);
+    const double scale = ldexp(1.0, kb);
+    const double inv_scale = ldexp(1.0, -kb);
+    const int tx = tid & 15, ty = tid >> 4;
+
+    double pj[4][4], best[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const double pi = pd[row0 + ty + 16 * a] * scale;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int c = tx + 16 * b;
+            pj[a][b] = c < nJ ? pi * pd[col0 + c + 1] : 0.0;
+            best[a][b] = __builtin_inf();
+        }
+    }
+
+    // Staging: A block is T rows x KC columns, B block KC rows x T columns;
+    // 4 elements of each per thread.
+    int64_t ra[4], rb[4];
+    double rp = 0.0;
+    auto load = [&](int kc) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + NTH * u;
+            const int r = e / KC, kk = e % KC;
+            const int k = kc + kk;
+            ra[u] = k < kend ? m[(size_t)(row0 + r) * n + k] : 0;
+            const int kk2 = e / T, c = e % T;
+            const int k2 = kc + kk2;
+            rb[u] = (k2 < kend && c < nJ) ? m[(size_t)(k2 + 1) * n + col0 + c] : 0;
+        }
+        if (tid < KC) rp = (kc + tid < kend) ? pd[kc + tid + 1] : 0.0;
+    };
+    auto store = [&](int kc, int buf) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + NTH * u;
+            const int r = e / KC, kk = e % KC;
+            As[buf][kk][r] = (kc + kk < kend) ? (double)ra[u] * scale : kPad;
+            const int kk2 = e / T, c = e % T;
+            Bs[buf][kk2][c] = fma((double)rb[u], scale, (double)(kc + kk2 - k0));
+        }
+        if (tid < KC) Ps[buf][tid] = rp;
+    };
+
+    load(k0);
+    store(k0, 0);
+    __syncthreads();
+    int buf = 0;
+    for (int kc = k0; kc < kend; kc += KC) {
+        const bool more = kc + KC < kend;
+        if (more) load(kc + KC);
+#pragma unroll 4
+        for (int kk = 0; kk < KC; ++kk) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = As[buf][kk][ty + 16 * a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = Bs[buf][kk][tx + 16 * b];
+            const double pk = Ps[buf][kk];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    best[a][b] = fmin(best[a][b], fma(pj[a][b], pk, bv[b]) + av[a]);
+        }
+        if (more) store(kc + KC, buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+
+    uint64_t *out = part + (size_t)blockIdx.x * T * T;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int r = ty + 16 * a, c = tx + 16 * b;
+            uint64_t packed = UINT64_MAX;
+            if (c < nJ) {
+                const double key = best[a][b];
+                const double cost = floor(key * inv_scale);
+                const int kl = (int)fma(-cost, scale, key);
+                packed = ((uint64_t)cost << kbits) | (uint64_t)(k0 + kl);
+            }
+            out[r * T + c] = packed;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Closure of tile-diagonal D >= 1: one workgroup per tile (I, I+D).
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(NTH) void k_close(int64_t *__restrict__ m, int32_t *__restrict__ s,
+                                               const double *__restrict__ pd, int32_t n,
+                                               int32_t D, int32_t P, int32_t kb, int32_t kbits,
+                                               const uint64_t *__restrict__ part)
+{
+    __shared__ double DIs[T][T + 1];  // DI[r][q] * 2^kb + q        (q >= r)
+    __shared__ double DJs[T][T + 1];  // DJ[q][c] * 2^kb + T + q - 1 (1 <= q <= c)
+    __shared__ double Xs[T][T + 1];   // bulk key, then final cost * 2^kb
+    __shared__ int32_t Ks[T][T];      // bulk split, then final split
+    __shared__ double pI[T];          // p[row0 + q]
+    __shared__ double pJ[T + 1];      // p[col0 + q]
+
+    const int tid = threadIdx.x;
+    const int I = blockIdx.x, J = I + D;
+    const int row0 = I * T, col0 = J * T;
+    const int nJ = min(T, n - col0);
+    const double scale = ldexp(1.0, kb);
+    const double inv_scale = ldexp(1.0, -kb);
+    const uint64_t kmask = (((uint64_t)1) << kbits) - 1;
+
+    for (int q = tid; q < T; q += NTH) pI[q] = pd[row0 + q];
+    for (int q = tid; q <= T; q += NTH) pJ[q] = q <= nJ ? pd[col0 + q] : 0.0;
+    for (int idx = tid; idx < T * T; idx += NTH) {
+        const int r = idx / T, q = idx % T;
+        if (q >= r) DIs[r][q] = fma((double)m[(size_t)(row0 + r) * n + row0 + q], scale, (double)q);
+        // DJs is indexed [q][c]: here r plays q and q plays c.
+        if (r >= 1 && r <= q && q < nJ)
+            DJs[r][q] = fma((double)m[(size_t)(col0 + r) * n + col0 + q], scale, (double)(T + r - 1));
+    }
+    // Bulk result per cell: packed (cost << kbits | k) partials, or for
+    // D == 1 the single bulk split k = (I+1)T-1 (both operands in the
+    // diagonal tiles).
+    for (int idx = tid; idx < T * T; idx += NTH) {
+        const int r = idx / T, c = idx % T;
+        if (c >= nJ) continue;
+        int64_t cost;
+        int32_t k;
+        if (D == 1) {
+            k = row0 + T - 1;
+            cost = m[(size_t)(row0 + r) * n + k] + m[(size_t)(k + 1) * n + col0 + c] +
+                   (int64_t)pd[row0 + r] * (int64_t)pd[k + 1] * (int64_t)pd[col0 + c + 1];
+        } else {
+            uint64_t key = UINT64_MAX;
+            const uint64_t *src = part + ((size_t)I * P) * T * T + idx;
+            for (int ch = 0; ch < P; ++ch) {
+                const uint64_t v = src[(size_t)ch * T * T];
+                key = v < key ? v : key;
+            }
+            cost = (int64_t)(key >> kbits);
+            k = (int32_t)(key & kmask);
+        }
+        Xs[r][c] = fma((double)cost, scale, (double)(T - 1));
+        Ks[r][c] = k;
+    }
+    __syncthreads();
+
+    const int e = tid >> 2, g = tid & 3;
+    const int wmax = (T - 1) + (nJ - 1);
+    for (int w = 0; w <= wmax; ++w) {
+        const int c_lo = max(0, w - (T - 1));
+        const int c_hi = min(w, nJ - 1);
+        const int c = c_lo + e;
+        const int r = T - 1 - w + c;
+        const bool act = c <= c_hi;
+        double best = __builtin_inf();
+        if (act) {
+            const double PJ = pI[r] * pJ[c + 1] * scale;
+            const int na = T - 1 - r;
+            for (int u = g; u < w; u += 4) {
+                double x;
+                if (u < na) {
+                    const int rp = r + 1 + u;
+                    x = fma(PJ, pI[rp], DIs[r][rp - 1]) + Xs[rp][c];
+                } else {
+                    const int cp = u - na;
+                    x = fma(PJ, pJ[cp + 1], DJs[cp + 1][c]) + Xs[r][cp];
+                }
+                best = fmin(best, x);
+            }
+        }
+        best = fmin(best, __shfl_xor(best, 1, 4));
+        best = fmin(best, __shfl_xor(best, 2, 4));
+        if (act && g == 0) {
+            const double fin = fmin(best, Xs[r][c]);
+            const double cost = floor(fin * inv_scale);
+            const int kl = (int)fma(-cost, scale, fin);
+            Xs[r][c] = cost * scale;
+            if (kl != T - 1) Ks[r][c] = kl < T - 1 ? row0 + kl : col0 + (kl - T);
+        }
+        __syncthreads();
+    }
+
+    for (int idx = tid; idx < T * T; idx += NTH) {
+        const int r = idx / T, c = idx % T;
+        if (c < nJ) {
+            const size_t o = (size_t)(row0 + r) * n + col0 + c;
+            m[o] = (int64_t)(Xs[r][c] * inv_scale);
+            s[o] = Ks[r][c];
+        }
+    }
+    for (int idx = tid; idx < T * T; idx += NTH) {
+        const int c = idx / T, r = idx % T;
+        if (c < nJ) {
+            const size_t o = (size_t)(col0 + c) * n + row0 + r;
+            m[o] = (int64_t)(Xs[r][c] * inv_scale);
+            s[o] = -1;
+        }
+    }
+}
+
+struct Plan {
+    int32_t NT = 0, kb = 0, kbits = 0;
+};
+
+// Chunking of the bulk range of tile-diagonal D: P chunks of KS splits.
+void bulk_split(int32_t NT, int32_t D, int32_t kb, int32_t *KS, int32_t *P)
+{
+    const int32_t tiles = NT - D;
+    const int32_t L = (D - 1) * T + 1;
+    const int32_t target_groups = 1024;
+    int32_t want = (target_groups + tiles - 1) / tiles;
+    int32_t maxp = (L + 63) / 64;  // at least 64 splits per chunk
+    if (maxp > 32) maxp = 32;
+    if (want > maxp) want = maxp;
+    if (want < 1) want = 1;
+    int32_t ks = (L + want - 1) / want;
+    ks = (ks + KC - 1) / KC * KC;
+    const int32_t cap = kb >= 30 ? (1 << 30) : (1 << kb);
+    if (ks > cap) ks = cap / KC * KC;
+    *KS = ks;
+    *P = (L + ks - 1) / ks;
+}
+
+int32_t bitlen_u64(uint64_t v)
+{
+    int32_t b = 0;
+    while (v) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
+
+}  // namespace
+
+bool tiled_accepts(const ChainInfo &ci)
+{
+    const int32_t kbits = bitlen_u64((uint64_t)(ci.n > 1 ? ci.n - 1 : 1));
+    return ci.cost_bits + 7 <= 53 && ci.cost_bits + kbits <= 64;
+}
+
+mcm_status run_tiled(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int32_t *s,
+                     hipStream_t stream)
+{
+    if (!tiled_accepts(ci)) return MCM_ERR_UNSUPPORTED;
+    const int32_t n = ci.n;
+    Plan pl;
+    pl.NT = (n + T - 1) / T;
+    pl.kb = 53 - ci.cost_bits;
+    if (pl.kb > 20) pl.kb = 20;
+    pl.kbits = bitlen_u64((uint64_t)(n > 1 ? n - 1 : 1));
+
+    // Partial buffer: the largest tile-diagonal.
+    size_t part_elems = 0;
+    for (int32_t D = 2; D < pl.NT; ++D) {
+        int32_t KS, P;
+        bulk_split(pl.NT, D, pl.kb, &KS, &P);
+        const size_t e = (size_t)(pl.NT - D) * P * T * T;
+        if (e > part_elems) part_elems = e;
+    }
+    uint64_t *part = nullptr;
+    if (part_elems) {
+        if (ws_alloc((void **)&part, part_elems * sizeof(uint64_t), stream) != hipSuccess)
+            return MCM_ERR_NO_MEMORY;
+    }
+    mcm_status st = MCM_OK;
+    {
+        // Split evaluations inside the diagonal tiles: sum over tiles of
+        // (nI^3 - nI) / 6.
+        double ev = 0.0;
+        for (int32_t I = 0; I < pl.NT; ++I) {
+            const double nI = (double)((n - I * T) < T ? (n - I * T) : T);
+            ev += (nI * nI * nI - nI) / 6.0;
+        }
+        ProfileScope ps(KC_SETUP, stream, ev);
+        hipLaunchKernelGGL(k_tri, dim3(pl.NT), dim3(NTH), 0, stream, dc.p, n, m, s);
+        if (hipGetLastError() != hipSuccess) st = MCM_ERR_DEVICE;
+    }
+    for (int32_t D = 1; D < pl.NT && st == MCM_OK; ++D) {
+        const int32_t tiles = pl.NT - D;
+        const int32_t nlast = n - (pl.NT - 1) * T;  // valid columns of the last tile
+        const double cells = (double)(tiles - 1) * T * T + (double)T * nlast;
+        int32_t KS = 0, P = 0;
+        if (D >= 2) {
+            bulk_split(pl.NT, D, pl.kb, &KS, &P);
+            const double L = (double)(D - 1) * T + 1;
+            ProfileScope ps(KC_BULK, stream, cells * L);
+            hipLaunchKernelGGL(k_bulk, dim3(tiles * P), dim3(NTH), 0, stream, m, dc.pd, n, D, KS,
+                               P, pl.kb, pl.kbits, part);
+            if (hipGetLastError() != hipSuccess) {
+                st = MCM_ERR_DEVICE;
+                break;
+            }
+        }
+        {
+            // Closure evaluations: (a) and (b) splits, plus the single bulk
+            // split when D == 1.  Per tile: sum over cells of (T-1-r) + c.
+            const double per_full = (double)T * T * (T - 1);
+            const double per_last = (double)nlast * T * (T - 1) / 2.0 +
+                                    (double)T * nlast * (nlast - 1) / 2.0;
+            double ev = (double)(tiles - 1) * per_full + per_last;
+            if (D == 1) ev += cells;
+            ProfileScope ps(KC_CLOSE, stream, ev);
+            hipLaunchKernelGGL(k_close, dim3(tiles), dim3(NTH), 0, stream, m, s, dc.pd, n, D, P,
+                               pl.kb, pl.kbits, part);
+            if (hipGetLastError() != hipSuccess) st = MCM_ERR_DEVICE;
+        }
+    }
+    if (part) ws_free(part, stream);
+    return st;
+}
+
+}  // namespace mcm

@@ -1,0 +1,311 @@
+// C ABI layer: validation, chain upload, path selection, workspace and the
+// kernel-level profiler.  Every entry point validates its host arguments
+// before making any HIP call, so invalid input never touches the device.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <mutex>
+#include <new>
+#include <string.h>
+#include <unordered_map>
+#include <vector>
+
+#include "mcm_internal.h"
+
+namespace mcm {
+namespace {
+
+// ------------------------------------------------------------------------
+// Validation.
+// ------------------------------------------------------------------------
+mcm_status check_chain(const int32_t *p, int32_t n, ChainInfo *ci)
+{
+    if (p == nullptr || n < 1) return MCM_ERR_INVALID_ARG;
+    int32_t pmax = 0;
+    for (int32_t t = 0; t <= n; ++t) {
+        if (p[t] < 1) return MCM_ERR_INVALID_ARG;
+        if (p[t] > pmax) pmax = p[t];
+    }
+    unsigned __int128 bound = (unsigned __int128)(uint64_t)pmax * (uint64_t)pmax;
+    bound *= (uint64_t)pmax;
+    bound *= (uint64_t)(n - 1);
+    if (bound >= ((unsigned __int128)1 << 63)) return MCM_ERR_OVERFLOW;
+    int32_t bits = 0;
+    for (unsigned __int128 v = bound; v; v >>= 1) ++bits;
+    if (ci) {
+        ci->n = n;
+        ci->pmax = pmax;
+        ci->cost_bits = bits;
+    }
+    return MCM_OK;
+}
+
+// ------------------------------------------------------------------------
+// Pinned staging for the host chain: a grow-only pool of pinned buffers,
+// each guarded by an event recorded after its upload; a buffer is reused
+// once its event has completed.
+// ------------------------------------------------------------------------
+struct StagingBuf {
+    void *host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    int device = -1;
+    bool claimed = false;
+};
+
+std::mutex g_stage_mu;
+std::vector<StagingBuf *> g_stage;
+
+StagingBuf *stage_acquire(size_t bytes, int device)
+{
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    for (StagingBuf *b : g_stage) {
+        if (b->claimed || b->device != device || b->bytes < bytes) continue;
+        if (hipEventQuery(b->done) != hipSuccess) continue;
+        b->claimed = true;
+        return b;
+    }
+    size_t cap = 64 * 1024;
+    while (cap < bytes) cap <<= 1;
+    StagingBuf *b = new (std::nothrow) StagingBuf;
+    if (!b) return nullptr;
+    if (hipHostMalloc(&b->host, cap, hipHostMallocDefault) != hipSuccess) {
+        delete b;
+        return nullptr;
+    }
+    if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(b->host);
+        delete b;
+        return nullptr;
+    }
+    b->bytes = cap;
+    b->device = device;
+    b->claimed = true;
+    g_stage.push_back(b);
+    return b;
+}
+
+void stage_release(StagingBuf *b)
+{
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    b->claimed = false;
+}
+
+// ------------------------------------------------------------------------
+// Stream-ordered workspace: hipMallocAsync from the device's default pool,
+// with the pool told to keep freed memory cached.
+// ------------------------------------------------------------------------
+std::mutex g_pool_mu;
+std::unordered_map<int, bool> g_pool_ready;
+
+void pool_setup(int device)
+{
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (g_pool_ready[device]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    g_pool_ready[device] = true;
+}
+
+// ------------------------------------------------------------------------
+// Profiler state.
+// ------------------------------------------------------------------------
+struct ProfRecord {
+    int cls;
+    hipEvent_t start, stop;
+    double evals;
+};
+std::atomic<int> g_prof_on{0};
+std::mutex g_prof_mu;
+std::vector<ProfRecord> g_prof_pending;
+double g_prof_ms[KC_COUNT];
+int64_t g_prof_launches[KC_COUNT];
+double g_prof_evals[KC_COUNT];
+
+void prof_clear_locked()
+{
+    for (auto &r : g_prof_pending) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    g_prof_pending.clear();
+    for (int c = 0; c < KC_COUNT; ++c) {
+        g_prof_ms[c] = 0.0;
+        g_prof_launches[c] = 0;
+        g_prof_evals[c] = 0.0;
+    }
+}
+
+void prof_drain_locked()
+{
+    for (auto &r : g_prof_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.stop) == hipSuccess &&
+            hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+            g_prof_ms[r.cls] += ms;
+            g_prof_launches[r.cls] += 1;
+            g_prof_evals[r.cls] += r.evals;
+        }
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    g_prof_pending.clear();
+}
+
+mcm_status upload_chain(const int32_t *p, int32_t n, hipStream_t stream, void **dev_block,
+                        DeviceChain *dc)
+{
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return MCM_ERR_DEVICE;
+    pool_setup(device);
+    // Layout: n+1 int32 (padded to 8 bytes), then n+1 doubles.
+    const size_t np = (size_t)n + 1;
+    const size_t off_d = (np * sizeof(int32_t) + 7) / 8 * 8;
+    const size_t bytes = off_d + np * sizeof(double);
+    StagingBuf *sb = stage_acquire(bytes, device);
+    if (!sb) return MCM_ERR_NO_MEMORY;
+    memcpy(sb->host, p, np * sizeof(int32_t));
+    double *hd = (double *)((char *)sb->host + off_d);
+    for (size_t t = 0; t < np; ++t) hd[t] = (double)p[t];
+    void *dev = nullptr;
+    if (ws_alloc(&dev, bytes, stream) != hipSuccess) {
+        stage_release(sb);
+        return MCM_ERR_NO_MEMORY;
+    }
+    hipError_t e = hipMemcpyAsync(dev, sb->host, bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(sb->done, stream);
+    stage_release(sb);
+    if (e != hipSuccess) {
+        ws_free(dev, stream);
+        return MCM_ERR_DEVICE;
+    }
+    *dev_block = dev;
+    dc->p = (const int32_t *)dev;
+    dc->pd = (const double *)((char *)dev + off_d);
+    return MCM_OK;
+}
+
+}  // namespace
+
+hipError_t ws_alloc(void **ptr, size_t bytes, hipStream_t stream)
+{
+    return hipMallocAsync(ptr, bytes ? bytes : 1, stream);
+}
+
+void ws_free(void *ptr, hipStream_t stream)
+{
+    if (ptr) (void)hipFreeAsync(ptr, stream);
+}
+
+ProfileScope::ProfileScope(int cls, hipStream_t stream, double evals)
+    : cls_(cls), stream_(stream), evals_(evals)
+{
+    if (!g_prof_on.load(std::memory_order_relaxed)) return;
+    if (hipEventCreate(&start_) != hipSuccess) {
+        start_ = nullptr;
+        return;
+    }
+    if (hipEventRecord(start_, stream_) != hipSuccess) {
+        (void)hipEventDestroy(start_);
+        start_ = nullptr;
+    }
+}
+
+ProfileScope::~ProfileScope()
+{
+    if (!start_) return;
+    hipEvent_t stop = nullptr;
+    if (hipEventCreate(&stop) != hipSuccess || hipEventRecord(stop, stream_) != hipSuccess) {
+        if (stop) (void)hipEventDestroy(stop);
+        (void)hipEventDestroy(start_);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_pending.push_back({cls_, start_, stop, evals_});
+}
+
+}  // namespace mcm
+
+using namespace mcm;
+
+extern "C" {
+
+const char *mcm_status_string(int32_t status)
+{
+    switch (status) {
+    case MCM_OK: return "ok";
+    case MCM_ERR_INVALID_ARG: return "invalid argument";
+    case MCM_ERR_OVERFLOW: return "costs may overflow int64: (n-1)*max(p)^3 >= 2^63";
+    case MCM_ERR_NO_MEMORY: return "out of memory";
+    case MCM_ERR_DEVICE: return "HIP device error";
+    case MCM_ERR_UNSUPPORTED: return "the requested kernel path does not accept this input";
+    default: return "unknown status";
+    }
+}
+
+int32_t mcm_version(void) { return 100; }
+
+mcm_status mcm_check_chain(const int32_t *p, int32_t n) { return check_chain(p, n, nullptr); }
+
+int32_t mcm_select_algo(const int32_t *p, int32_t n)
+{
+    ChainInfo ci;
+    mcm_status st = check_chain(p, n, &ci);
+    if (st != MCM_OK) return -(int32_t)st;
+    return tiled_accepts(ci) ? MCM_ALGO_TILED : MCM_ALGO_WAVEFRONT;
+}
+
+mcm_status mcm_solve_algo(const int32_t *p, int32_t n, int64_t *m_out, int32_t *s_out,
+                          int32_t algo, hipStream_t stream)
+{
+    ChainInfo ci;
+    mcm_status st = check_chain(p, n, &ci);
+    if (st != MCM_OK) return st;
+    if (m_out == nullptr || s_out == nullptr) return MCM_ERR_INVALID_ARG;
+    if (((uintptr_t)m_out & 7) != 0 || ((uintptr_t)s_out & 3) != 0) return MCM_ERR_INVALID_ARG;
+    if (algo == MCM_ALGO_AUTO) algo = tiled_accepts(ci) ? MCM_ALGO_TILED : MCM_ALGO_WAVEFRONT;
+    if (algo != MCM_ALGO_WAVEFRONT && algo != MCM_ALGO_TILED) return MCM_ERR_INVALID_ARG;
+    if (algo == MCM_ALGO_TILED && !tiled_accepts(ci)) return MCM_ERR_UNSUPPORTED;
+
+    if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
+    void *chain_block = nullptr;
+    DeviceChain dc;
+    st = upload_chain(p, n, stream, &chain_block, &dc);
+    if (st != MCM_OK) return st;
+    if (algo == MCM_ALGO_TILED)
+        st = run_tiled(dc, ci, m_out, s_out, stream);
+    else
+        st = run_wavefront(dc, ci, m_out, s_out, stream);
+    ws_free(chain_block, stream);
+    return st;
+}
+
+mcm_status mcm_solve(const int32_t *p, int32_t n, int64_t *m_out, int32_t *s_out,
+                     hipStream_t stream)
+{
+    return mcm_solve_algo(p, n, m_out, s_out, MCM_ALGO_AUTO, stream);
+}
+
+void mcm_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_clear_locked();
+    g_prof_on.store(on ? 1 : 0);
+}
+
+mcm_status mcm_profile_read(int32_t kernel_class, double *total_ms, int64_t *launches,
+                            double *split_evals)
+{
+    if (kernel_class < 0 || kernel_class >= KC_COUNT) return MCM_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_drain_locked();
+    if (total_ms) *total_ms = g_prof_ms[kernel_class];
+    if (launches) *launches = g_prof_launches[kernel_class];
+    if (split_evals) *split_evals = g_prof_evals[kernel_class];
+    return MCM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+"""The C ABI library on the CPU: it loads, exports every declared symbol,
+and rejects bad input before any device call (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2008_01938_amd import binding, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mcm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mcm_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.lib_path()):
+        pytest.skip("libmcm.so not built")
+    return binding.load()
+
+
+def test_header_declares_expected_functions():
+    assert _declared_functions() == sorted(binding.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for st in range(6):
+        assert binding.status_string(st)
+    assert binding.status_string(99) == "unknown status"
+    assert binding.version() >= 100
+
+
+def test_check_chain(lib):
+    assert binding.check_chain([3, 4]) == binding.OK
+    assert binding.check_chain([3]) == binding.ERR_INVALID_ARG          # n = 0
+    assert binding.check_chain([3, 0, 4]) == binding.ERR_INVALID_ARG
+    assert binding.check_chain([3, -1, 4]) == binding.ERR_INVALID_ARG
+    big = 1 << 21
+    assert binding.check_chain([big] * 3) == binding.ERR_OVERFLOW
+    assert binding.check_chain([big - 1] * 3) == binding.OK
+    assert lib.mcm_check_chain(None, 4) == binding.ERR_INVALID_ARG
+
+
+def test_select_algo(lib):
+    assert binding.select_algo(workloads.single_n8192()) == binding.ALGO_TILED
+    assert binding.select_algo(workloads.single_n128()) == binding.ALGO_TILED
+    # (n-1) * pmax^3 >= 2^46 leaves too few fp64 bits: int64 wavefront.
+    assert binding.select_algo([1 << 16] * 5) == binding.ALGO_WAVEFRONT
+    assert binding.select_algo([0, 1]) == -binding.ERR_INVALID_ARG
+    assert binding.select_algo([1 << 21] * 3) == -binding.ERR_OVERFLOW
+
+
+def _solve_raw(lib, p, m_ptr, s_ptr, algo=0):
+    a = np.ascontiguousarray(np.asarray(p, dtype=np.int32))
+    return lib.mcm_solve_algo(a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), a.size - 1,
+                              ctypes.c_void_p(m_ptr), ctypes.c_void_p(s_ptr), algo,
+                              ctypes.c_void_p(0))
+
+
+def test_solve_rejects_bad_input_before_device(lib):
+    # Host buffers stand in for device pointers: validation must fail before
+    # anything is enqueued, so they are never touched.
+    m = np.full(16, 7, dtype=np.int64)
+    s = np.full(16, 7, dtype=np.int32)
+    mp, sp = m.ctypes.data, s.ctypes.data
+    assert _solve_raw(lib, [3], mp, sp) == binding.ERR_INVALID_ARG
+    assert _solve_raw(lib, [3, 0, 2], mp, sp) == binding.ERR_INVALID_ARG
+    assert _solve_raw(lib, [1 << 21] * 3, mp, sp) == binding.ERR_OVERFLOW
+    assert _solve_raw(lib, [2, 3, 4], 0, sp) == binding.ERR_INVALID_ARG
+    assert _solve_raw(lib, [2, 3, 4], mp, 0) == binding.ERR_INVALID_ARG
+    assert _solve_raw(lib, [2, 3, 4], mp + 4, sp) == binding.ERR_INVALID_ARG   # misaligned
+    assert _solve_raw(lib, [2, 3, 4], mp, sp + 2) == binding.ERR_INVALID_ARG
+    assert _solve_raw(lib, [2, 3, 4], mp, sp, algo=9) == binding.ERR_INVALID_ARG
+    assert _solve_raw(lib, [1 << 16] * 5, mp, sp, algo=binding.ALGO_TILED) == \
+        binding.ERR_UNSUPPORTED
+    assert np.all(m == 7) and np.all(s == 7)
+
+
+def test_profile_read_rejects_bad_class(lib):
+    d = ctypes.c_double()
+    n = ctypes.c_int64()
+    assert lib.mcm_profile_read(99, ctypes.byref(d), ctypes.byref(n), ctypes.byref(d)) == \
+        binding.ERR_INVALID_ARG

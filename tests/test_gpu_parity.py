@@ -1,0 +1,209 @@
+"""GPU path vs the CPU oracle, bit-exact (integers: tolerance 0).
+
+Every case prints its name, shape and kernel path before touching the GPU
+so a failing run can be attributed.  Whole n x n buffers are compared
+wherever the oracle can fill the table in seconds; at n = 8192 the check
+uses sampled cells, oracle windows and properties that hold at any size.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_01938_amd import binding, workloads
+
+pytestmark = pytest.mark.gpu
+
+ALGOS = ["wavefront", "tiled"]
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_solve(p, algo="auto"):
+    import torch
+    _say(f"[gpu] solve n={len(p) - 1} algo={algo} pmax={int(np.max(p))}")
+    m, s = binding.solve(p, algo=algo)
+    torch.cuda.synchronize()
+    return m.cpu().numpy(), s.cpu().numpy()
+
+
+def assert_tables_equal(p, algo, threads=None):
+    m, s = gpu_solve(p, algo)
+    om, os_ = oracle.fill(p, threads=threads or oracle.default_threads())
+    if not np.array_equal(m, om):
+        bad = np.argwhere(m != om)
+        i, j = bad[0]
+        raise AssertionError(f"m differs at {len(bad)} cells, first ({i},{j}): "
+                             f"gpu {m[i, j]} oracle {om[i, j]}")
+    if not np.array_equal(s, os_):
+        bad = np.argwhere(s != os_)
+        i, j = bad[0]
+        raise AssertionError(f"s differs at {len(bad)} cells, first ({i},{j}): "
+                             f"gpu {s[i, j]} oracle {os_[i, j]}")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    binding.load()
+
+
+# Sizes around the tile edge (64) and its multiples: empty tile-diagonals,
+# one tile, ragged last tile, several tile-diagonals with split chunks.
+SIZES = [1, 2, 3, 4, 5, 7, 16, 33, 63, 64, 65, 100, 127, 128, 129, 191, 192, 193, 255, 257, 300,
+         450]
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("n", SIZES)
+def test_random_dims(algo, n):
+    assert_tables_equal(workloads.uniform_dims(n, 1, 1024, 9000 + n), algo)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("n", [6, 64, 130, 333])
+def test_tie_heavy_dims(algo, n):
+    assert_tables_equal(workloads.tie_heavy(n, 300 + n), algo)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("maker", ["all_equal", "increasing", "decreasing", "alternating"])
+def test_structured_dims(algo, maker):
+    n = 257
+    p = {"all_equal": lambda: workloads.all_equal(n, 1024),
+         "increasing": lambda: workloads.increasing(n),
+         "decreasing": lambda: workloads.decreasing(n),
+         "alternating": lambda: workloads.alternating(n)}[maker]()
+    assert_tables_equal(p, algo)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_config_n128(algo):
+    assert_tables_equal(workloads.single_n128(), algo)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_config_n2048(algo):
+    assert_tables_equal(workloads.single_n2048(), algo)
+
+
+def test_wavefront_large_values():
+    # Costs near 2^62: beyond the fp64-exact range of the tiled path.
+    p = workloads.uniform_dims(32, (1 << 19) - 50, 1 << 19, 5)
+    assert binding.select_algo(p) == binding.ALGO_WAVEFRONT
+    assert_tables_equal(p, "auto")
+    with pytest.raises(binding.MCMError) as ei:
+        binding.solve(p, algo="tiled")
+    assert ei.value.status == binding.ERR_UNSUPPORTED
+
+
+def test_tiled_at_its_range_limit():
+    # (n-1) * pmax^3 just under 2^46: the fewest fp64 bits the tiled path
+    # accepts (7 bits of split index left).
+    n = 300
+    pmax = int(((1 << 46) // (n - 1)) ** (1 / 3)) - 1
+    p = workloads.uniform_dims(n, pmax - 20, pmax, 8)
+    assert binding.select_algo(p) == binding.ALGO_TILED
+    assert_tables_equal(p, "tiled")
+
+
+def test_profile_counts_every_split():
+    import torch
+    for algo, n in (("tiled", 300), ("wavefront", 150)):
+        p = workloads.uniform_dims(n, 1, 1024, 77)
+        binding.profile_enable(True)
+        gpu_solve(p, algo)
+        torch.cuda.synchronize()
+        total = sum(binding.profile_read(c)["split_evals"] for c in range(5))
+        binding.profile_enable(False)
+        assert total == (n ** 3 - n) // 6, (algo, total)
+
+
+def test_nondefault_stream_and_repeat_determinism():
+    import torch
+    p = workloads.uniform_dims(700, 1, 1024, 123)
+    st = torch.cuda.Stream()
+    outs = []
+    for _ in range(3):
+        with torch.cuda.stream(st):
+            m, s = binding.solve(p, algo="tiled", stream=st)
+        st.synchronize()
+        outs.append((m.cpu().numpy(), s.cpu().numpy()))
+    for m, s in outs[1:]:
+        assert np.array_equal(m, outs[0][0]) and np.array_equal(s, outs[0][1])
+    om, os_ = oracle.fill(p, threads=oracle.default_threads())
+    assert np.array_equal(outs[0][0], om) and np.array_equal(outs[0][1], os_)
+
+
+# --------------------------------------------------------------------------
+# n = 8192, the benchmark configuration, in the launch configuration the
+# benchmark times (algo auto -> tiled).
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def n8192():
+    p = workloads.single_n8192()
+    assert binding.select_algo(p) == binding.ALGO_TILED
+    m, s = gpu_solve(p, "auto")
+    return p, m, s
+
+
+def test_n8192_structure(n8192):
+    p, m, s = n8192
+    n = len(p) - 1
+    pi = p.astype(np.int64)
+    assert np.all(np.diag(m) == 0)
+    assert np.array_equal(m, m.T)
+    idx = np.arange(n - 1)
+    assert np.array_equal(m[idx, idx + 1], pi[:-2] * pi[1:-1] * pi[2:])
+    assert np.array_equal(s[idx, idx + 1], idx)
+    assert np.all(np.tril(s) == -1)
+    iu, ju = np.triu_indices(n, 1)
+    su = s[iu, ju]
+    assert np.all((su >= iu) & (su < ju))
+
+
+def test_n8192_windows_match_oracle(n8192):
+    # Optimal substructure: the table of a sub-chain is a block of the
+    # full table, so the oracle on windows checks every cell inside them.
+    p, m, s = n8192
+    rng = np.random.default_rng(8192)
+    n = len(p) - 1
+    for i0 in [0, n - 600] + list(rng.integers(0, n - 600, size=3)):
+        i0 = int(i0)
+        L = 600
+        _say(f"[cpu] oracle window i0={i0} L={L}")
+        wm, ws = oracle.fill(p[i0:i0 + L + 1], threads=oracle.default_threads())
+        assert np.array_equal(m[i0:i0 + L, i0:i0 + L], wm)
+        assert np.array_equal(s[i0:i0 + L, i0:i0 + L], np.where(ws >= 0, ws + i0, -1))
+
+
+def test_n8192_sampled_recurrence(n8192):
+    # The recurrence re-evaluated from the GPU table at sampled cells of
+    # every size class, including the full-chain cell (0, n-1).
+    p, m, s = n8192
+    n = len(p) - 1
+    rng = np.random.default_rng(1)
+    i = rng.integers(0, n - 1, size=4000)
+    d = np.minimum(rng.integers(1, n, size=4000), n - 1 - i)
+    d = np.maximum(d, 1)
+    cells = np.stack([i, i + d], axis=1)
+    cells = np.concatenate([cells, [[0, n - 1], [1, n - 1], [0, n - 2]]])
+    cells = cells[cells[:, 1] < n]
+    assert oracle.check_cells(p, m, s, cells, threads=oracle.default_threads()) == 0
+
+
+def test_n8192_all_equal_closed_form():
+    n, d = 8192, 1024
+    p = workloads.all_equal(n, d)
+    m, s = gpu_solve(p, "auto")
+    iu, ju = np.triu_indices(n, 1)
+    assert np.array_equal(m[iu, ju], (ju - iu).astype(np.int64) * d ** 3)
+    assert np.array_equal(s[iu, ju], iu.astype(np.int32))
+    assert m[0, n - 1] == 8795019280384
