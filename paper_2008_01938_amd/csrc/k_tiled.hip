@@ -217,18 +217,30 @@ __global__ __launch_bounds__(NTH) void k_bulk(const int64_t *__restrict__ m,
 
 // ------------------------------------------------------------------------
 // Closure of tile-diagonal D >= 1: one workgroup per tile (I, I+D).
+//
+// Row group r (G lanes) owns local row r.  At local anti-diagonal step w
+// it finalises cell (r, c), c = w - (T-1-r), from the bulk result and the
+// closure splits:
+//   (a) q in [r, T-2]:  DI[r][q] + X[q+1][c] + p_i p[row0+q+1] p_{j+1}
+//   (b) c' in [0, c-1]: X[r][c'] + DJ[c'+1][c] + p_i p[col0+c'+1] p_{j+1}
+// DI[r][.] never changes and X[r][c'] was finalised by this same group, so
+// lane g keeps the entries with q = g (mod G) and c' = g (mod G) in
+// registers; only X[q+1][c] (other rows) and DJ[c'+1][c] come from LDS.
+// One barrier per step publishes the new cell to the other rows.
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(NTH) void k_close(int64_t *__restrict__ m, int32_t *__restrict__ s,
+constexpr int CG = 8;               // lanes per row group
+constexpr int CTH = T * CG;          // 512 threads
+constexpr int CS = T / CG;           // register slots per lane
+
+__global__ __launch_bounds__(CTH) void k_close(int64_t *__restrict__ m, int32_t *__restrict__ s,
                                                const double *__restrict__ pd, int32_t n,
                                                int32_t D, int32_t P, int32_t kb, int32_t kbits,
                                                const uint64_t *__restrict__ part)
 {
-    __shared__ double DIs[T][T + 1];  // DI[r][q] * 2^kb + q        (q >= r)
     __shared__ double DJs[T][T + 1];  // DJ[q][c] * 2^kb + T + q - 1 (1 <= q <= c)
     __shared__ double Xs[T][T + 1];   // bulk key, then final cost * 2^kb
-    __shared__ int32_t Ks[T][T];      // bulk split, then final split
-    __shared__ double pI[T];          // p[row0 + q]
-    __shared__ double pJ[T + 1];      // p[col0 + q]
+    __shared__ int32_t Ks[T][T + 1];  // bulk split, then final split
+    __shared__ double pJs[T + 1];     // p[col0 + q]
 
     const int tid = threadIdx.x;
     const int I = blockIdx.x, J = I + D;
@@ -238,91 +250,114 @@ __global__ __launch_bounds__(NTH) void k_close(int64_t *__restrict__ m, int32_t 
     const double inv_scale = ldexp(1.0, -kb);
     const uint64_t kmask = (((uint64_t)1) << kbits) - 1;
 
-    for (int q = tid; q < T; q += NTH) pI[q] = pd[row0 + q];
-    for (int q = tid; q <= T; q += NTH) pJ[q] = q <= nJ ? pd[col0 + q] : 0.0;
-    for (int idx = tid; idx < T * T; idx += NTH) {
-        const int r = idx / T, q = idx % T;
-        if (q >= r) DIs[r][q] = fma((double)m[(size_t)(row0 + r) * n + row0 + q], scale, (double)q);
-        // DJs is indexed [q][c]: here r plays q and q plays c.
-        if (r >= 1 && r <= q && q < nJ)
-            DJs[r][q] = fma((double)m[(size_t)(col0 + r) * n + col0 + q], scale, (double)(T + r - 1));
+    const int r = tid / CG, g = tid % CG;
+    // Register-resident operands of row r.
+    double DIr[CS], pIr[CS], pJr[CS], Xrow[CS];
+    const double pi_s = pd[row0 + r] * scale;
+#pragma unroll
+    for (int t = 0; t < CS; ++t) {
+        const int q = t * CG + g;  // (a) split column q, (b) split column c' = q
+        const bool qa = q >= r && q <= T - 2;
+        DIr[t] = qa ? fma((double)m[(size_t)(row0 + r) * n + row0 + q], scale, (double)q) : 0.0;
+        pIr[t] = qa ? pd[row0 + q + 1] : 0.0;
+        pJr[t] = q < nJ ? pd[col0 + q + 1] : 0.0;
+        Xrow[t] = 0.0;
     }
-    // Bulk result per cell: packed (cost << kbits | k) partials, or for
-    // D == 1 the single bulk split k = (I+1)T-1 (both operands in the
-    // diagonal tiles).
-    for (int idx = tid; idx < T * T; idx += NTH) {
-        const int r = idx / T, c = idx % T;
-        if (c >= nJ) continue;
-        int64_t cost;
-        int32_t k;
-        if (D == 1) {
-            k = row0 + T - 1;
-            cost = m[(size_t)(row0 + r) * n + k] + m[(size_t)(k + 1) * n + col0 + c] +
-                   (int64_t)pd[row0 + r] * (int64_t)pd[k + 1] * (int64_t)pd[col0 + c + 1];
-        } else {
-            uint64_t key = UINT64_MAX;
-            const uint64_t *src = part + ((size_t)I * P) * T * T + idx;
-            for (int ch = 0; ch < P; ++ch) {
-                const uint64_t v = src[(size_t)ch * T * T];
-                key = v < key ? v : key;
+
+    for (int q = tid; q <= T; q += CTH) pJs[q] = q <= nJ ? pd[col0 + q] : 0.0;
+    for (int idx = tid; idx < T * T; idx += CTH) {
+        const int qq = idx / T, c = idx % T;
+        if (qq >= 1 && qq <= c && c < nJ)
+            DJs[qq][c] = fma((double)m[(size_t)(col0 + qq) * n + col0 + c], scale,
+                             (double)(T + qq - 1));
+    }
+    // Bulk result per cell: the minimum of P packed (cost << kbits | k)
+    // partials, or for D == 1 the single bulk split k = (I+1)T-1 whose
+    // operands both lie in the diagonal tiles.
+    constexpr int CPT = T * T / CTH;  // cells per thread
+    uint64_t key[CPT];
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) key[u] = UINT64_MAX;
+    if (D == 1) {
+        const int k = row0 + T - 1;
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int idx = tid + CTH * u;
+            const int rr = idx / T, c = idx % T;
+            if (c < nJ) {
+                const int64_t cost = m[(size_t)(row0 + rr) * n + k] +
+                                     m[(size_t)(k + 1) * n + col0 + c] +
+                                     (int64_t)pd[row0 + rr] * (int64_t)pd[k + 1] *
+                                         (int64_t)pd[col0 + c + 1];
+                key[u] = ((uint64_t)cost << kbits) | (uint64_t)k;
             }
-            cost = (int64_t)(key >> kbits);
-            k = (int32_t)(key & kmask);
         }
-        Xs[r][c] = fma((double)cost, scale, (double)(T - 1));
-        Ks[r][c] = k;
+    } else {
+        const uint64_t *src = part + ((size_t)I * P) * T * T + tid;
+        for (int ch = 0; ch < P; ++ch) {
+            uint64_t v[CPT];
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) v[u] = src[(size_t)ch * T * T + CTH * u];
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) key[u] = v[u] < key[u] ? v[u] : key[u];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int idx = tid + CTH * u;
+        const int rr = idx / T, c = idx % T;
+        if (c < nJ) {
+            Xs[rr][c] = fma((double)(int64_t)(key[u] >> kbits), scale, (double)(T - 1));
+            Ks[rr][c] = (int32_t)(key[u] & kmask);
+        }
     }
     __syncthreads();
 
-    const int e = tid >> 2, g = tid & 3;
     const int wmax = (T - 1) + (nJ - 1);
     for (int w = 0; w <= wmax; ++w) {
-        const int c_lo = max(0, w - (T - 1));
-        const int c_hi = min(w, nJ - 1);
-        const int c = c_lo + e;
-        const int r = T - 1 - w + c;
-        const bool act = c <= c_hi;
-        double best = __builtin_inf();
-        if (act) {
-            const double PJ = pI[r] * pJ[c + 1] * scale;
-            const int na = T - 1 - r;
-            for (int u = g; u < w; u += 4) {
-                double x;
-                if (u < na) {
-                    const int rp = r + 1 + u;
-                    x = fma(PJ, pI[rp], DIs[r][rp - 1]) + Xs[rp][c];
-                } else {
-                    const int cp = u - na;
-                    x = fma(PJ, pJ[cp + 1], DJs[cp + 1][c]) + Xs[r][cp];
-                }
-                best = fmin(best, x);
+        const int c = w - (T - 1 - r);
+        if (c >= 0 && c < nJ) {  // uniform across the row group
+            const double PJ = pi_s * pJs[c + 1];
+            double best = __builtin_inf();
+#pragma unroll
+            for (int t = 0; t < CS; ++t) {
+                const int q = t * CG + g;
+                if (q >= r && q <= T - 2)
+                    best = fmin(best, fma(PJ, pIr[t], DIr[t]) + Xs[q + 1][c]);
+                if (q < c)
+                    best = fmin(best, fma(PJ, pJr[t], DJs[q + 1][c]) + Xrow[t]);
             }
-        }
-        best = fmin(best, __shfl_xor(best, 1, 4));
-        best = fmin(best, __shfl_xor(best, 2, 4));
-        if (act && g == 0) {
+            best = fmin(best, __shfl_xor(best, 1, CG));
+            best = fmin(best, __shfl_xor(best, 2, CG));
+            best = fmin(best, __shfl_xor(best, 4, CG));
             const double fin = fmin(best, Xs[r][c]);
             const double cost = floor(fin * inv_scale);
+            const double xv = cost * scale;
             const int kl = (int)fma(-cost, scale, fin);
-            Xs[r][c] = cost * scale;
-            if (kl != T - 1) Ks[r][c] = kl < T - 1 ? row0 + kl : col0 + (kl - T);
+#pragma unroll
+            for (int t = 0; t < CS; ++t)
+                if (t * CG + g == c) Xrow[t] = xv;
+            if (g == 0) {
+                Xs[r][c] = xv;
+                if (kl != T - 1) Ks[r][c] = kl < T - 1 ? row0 + kl : col0 + (kl - T);
+            }
         }
         __syncthreads();
     }
 
-    for (int idx = tid; idx < T * T; idx += NTH) {
-        const int r = idx / T, c = idx % T;
+    for (int idx = tid; idx < T * T; idx += CTH) {
+        const int rr = idx / T, c = idx % T;
         if (c < nJ) {
-            const size_t o = (size_t)(row0 + r) * n + col0 + c;
-            m[o] = (int64_t)(Xs[r][c] * inv_scale);
-            s[o] = Ks[r][c];
+            const size_t o = (size_t)(row0 + rr) * n + col0 + c;
+            m[o] = (int64_t)(Xs[rr][c] * inv_scale);
+            s[o] = Ks[rr][c];
         }
     }
-    for (int idx = tid; idx < T * T; idx += NTH) {
-        const int c = idx / T, r = idx % T;
+    for (int idx = tid; idx < T * T; idx += CTH) {
+        const int c = idx / T, rr = idx % T;
         if (c < nJ) {
-            const size_t o = (size_t)(col0 + c) * n + row0 + r;
-            m[o] = (int64_t)(Xs[r][c] * inv_scale);
+            const size_t o = (size_t)(col0 + c) * n + row0 + rr;
+            m[o] = (int64_t)(Xs[rr][c] * inv_scale);
             s[o] = -1;
         }
     }
@@ -431,7 +466,7 @@ mcm_status run_tiled(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int
             double ev = (double)(tiles - 1) * per_full + per_last;
             if (D == 1) ev += cells;
             ProfileScope ps(KC_CLOSE, stream, ev);
-            hipLaunchKernelGGL(k_close, dim3(tiles), dim3(NTH), 0, stream, m, s, dc.pd, n, D, P,
+            hipLaunchKernelGGL(k_close, dim3(tiles), dim3(CTH), 0, stream, m, s, dc.pd, n, D, P,
                                pl.kb, pl.kbits, part);
             if (hipGetLastError() != hipSuccess) st = MCM_ERR_DEVICE;
         }
