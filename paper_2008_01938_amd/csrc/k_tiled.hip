@@ -218,27 +218,96 @@ __global__ __launch_bounds__(NTH) void k_bulk(const int64_t *__restrict__ m,
 // ------------------------------------------------------------------------
 // Closure of tile-diagonal D >= 1: one workgroup per tile (I, I+D).
 //
-// Row group r (G lanes) owns local row r.  At local anti-diagonal step w
+// Row group r (CG lanes) owns local row r.  At local anti-diagonal step w
 // it finalises cell (r, c), c = w - (T-1-r), from the bulk result and the
 // closure splits:
 //   (a) q in [r, T-2]:  DI[r][q] + X[q+1][c] + p_i p[row0+q+1] p_{j+1}
 //   (b) c' in [0, c-1]: X[r][c'] + DJ[c'+1][c] + p_i p[col0+c'+1] p_{j+1}
 // DI[r][.] never changes and X[r][c'] was finalised by this same group, so
-// lane g keeps the entries with q = g (mod G) and c' = g (mod G) in
-// registers; only X[q+1][c] (other rows) and DJ[c'+1][c] come from LDS.
-// One barrier per step publishes the new cell to the other rows.
+// lane g keeps the entries with q = g (mod CG) and c' = g (mod CG) in
+// registers (slot t holds index t*CG + g); only X[q+1][c] (other rows) and
+// DJ[c'+1][c] come from LDS.  Slots that do not apply hold 2^62 in their
+// register operand, so their terms never win and need no select.  Wave h
+// covers rows 8h..8h+7, whose (a) splits all lie in slots >= h: the step
+// body is instantiated per wave index so that range is static.  Two waves
+// per SIMD hide the fp64 issue latency a single wave would expose.  All
+// LDS reads of a step are issued before the first use; the row group's
+// minimum is formed with DPP lane permutations; one barrier per step
+// publishes the new cells to the other rows.
 // ------------------------------------------------------------------------
 constexpr int CG = 8;               // lanes per row group
-constexpr int CTH = T * CG;          // 512 threads
+constexpr int CTH = T * CG;          // 512 threads = 8 waves, 2 per SIMD
 constexpr int CS = T / CG;           // register slots per lane
+constexpr int CROWS = 64 / CG;       // rows per wave
+constexpr int CSTR = T + 8;          // column stride (doubles) of the closure's LDS tables
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_perm(double v)
+{
+    const int2 b = __builtin_bit_cast(int2, v);
+    int2 o;
+    o.x = __builtin_amdgcn_update_dpp(0, b.x, CTRL, 0xF, 0xF, false);
+    o.y = __builtin_amdgcn_update_dpp(0, b.y, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, o);
+}
+
+// Minimum over each aligned group of CG = 8 lanes (all lanes active).
+__device__ __forceinline__ double min_group(double v)
+{
+    v = fmin(v, dpp_perm<0xB1>(v));   // quad_perm [1,0,3,2]: lane ^ 1
+    v = fmin(v, dpp_perm<0x4E>(v));   // quad_perm [2,3,0,1]: lane ^ 2
+    v = fmin(v, dpp_perm<0x141>(v));  // row_half_mirror: lane i <-> 7-i
+    return v;
+}
+
+struct CloseRegs {
+    double DIr[CS], PIr[CS], PJr[CS], Xrow[CS];
+};
+
+// One anti-diagonal step for wave H (rows 16H..16H+15).  Returns the
+// minimum over the closure splits of this lane's cell (before the bulk).
+template <int H>
+__device__ __forceinline__ double close_step(const CloseRegs &R, const double (*Xt)[CSTR],
+                                             const double (*DJt)[CSTR], int cc, int g,
+                                             double pJc)
+{
+    constexpr int T0 = H * (CROWS / CG);  // first (a) slot any row of this wave uses
+    double xa[CS], xb[CS];
+#pragma unroll
+    for (int t = T0; t < CS; ++t) xa[t] = Xt[cc][t * CG + g + 1];
+    // All (b) slots are read: DJt is zero outside its triangle, and a slot
+    // whose cell is not final yet still holds Xrow = 2^62.
+#pragma unroll
+    for (int t = 0; t < CS; ++t) xb[t] = DJt[cc][t * CG + g + 1];
+    // Independent terms, then a balanced min tree: a single running
+    // minimum would make every slot wait for the previous one.
+    double v[CS];
+#pragma unroll
+    for (int t = 0; t < CS; ++t) {
+        const double tb = fma(pJc, R.PJr[t], xb[t]) + R.Xrow[t];
+        v[t] = t >= T0 ? fmin(tb, fma(pJc, R.PIr[t], R.DIr[t]) + xa[t]) : tb;
+    }
+#pragma unroll
+    for (int span = 1; span < CS; span *= 2)
+#pragma unroll
+        for (int t = 0; t + span < CS; t += 2 * span) v[t] = fmin(v[t], v[t + span]);
+    return min_group(v[0]);
+}
 
 __global__ __launch_bounds__(CTH) void k_close(int64_t *__restrict__ m, int32_t *__restrict__ s,
                                                const double *__restrict__ pd, int32_t n,
                                                int32_t D, int32_t P, int32_t kb, int32_t kbits,
                                                const uint64_t *__restrict__ part)
 {
-    __shared__ double DJs[T][T + 1];  // DJ[q][c] * 2^kb + T + q - 1 (1 <= q <= c)
-    __shared__ double Xs[T][T + 1];   // bulk key, then final cost * 2^kb
+    // Column-major with a column stride of CSTR = 72 doubles.  LDS has 32
+    // banks of 4 bytes, so a 64-bit read is conflict-free when the 16 lanes
+    // served together touch distinct 8-byte words modulo 16.  In a step,
+    // lane (i, g) of a wave (row 8h+i) reads row t*CG+g+1 of column c_lo+i:
+    // word (c_lo+i)*72 + 8t+g+1 = 8i + g + const (mod 16), distinct for the
+    // 16 lanes i = 0..1, g = 0..7 of each group.  Row T is a spare so slot
+    // addresses never need clamping.
+    __shared__ double DJt[T][CSTR];  // DJt[c][q] = DJ[q][c] * 2^kb + T + q - 1 (1 <= q <= c), else 0
+    __shared__ double Xt[T][CSTR];   // Xt[c][q]: bulk key, then final cost * 2^kb of cell (q, c)
     __shared__ int32_t Ks[T][T + 1];  // bulk split, then final split
     __shared__ double pJs[T + 1];     // p[col0 + q]
 
@@ -251,24 +320,31 @@ __global__ __launch_bounds__(CTH) void k_close(int64_t *__restrict__ m, int32_t 
     const uint64_t kmask = (((uint64_t)1) << kbits) - 1;
 
     const int r = tid / CG, g = tid % CG;
-    // Register-resident operands of row r.
-    double DIr[CS], pIr[CS], pJr[CS], Xrow[CS];
+    const int h = __builtin_amdgcn_readfirstlane(tid / 64);  // rows CROWS*h ..
+    CloseRegs R;
     const double pi_s = pd[row0 + r] * scale;
 #pragma unroll
     for (int t = 0; t < CS; ++t) {
-        const int q = t * CG + g;  // (a) split column q, (b) split column c' = q
+        const int q = t * CG + g;  // (a) split column q; (b) split column c' = q
         const bool qa = q >= r && q <= T - 2;
-        DIr[t] = qa ? fma((double)m[(size_t)(row0 + r) * n + row0 + q], scale, (double)q) : 0.0;
-        pIr[t] = qa ? pd[row0 + q + 1] : 0.0;
-        pJr[t] = q < nJ ? pd[col0 + q + 1] : 0.0;
-        Xrow[t] = 0.0;
+        R.DIr[t] = qa ? fma((double)m[(size_t)(row0 + r) * n + row0 + q], scale, (double)q) : kPad;
+        R.PIr[t] = qa ? pi_s * pd[row0 + q + 1] : 0.0;
+        R.PJr[t] = q < nJ ? pi_s * pd[col0 + q + 1] : 0.0;
+        R.Xrow[t] = kPad;  // until cell (r, q) is final
     }
 
     for (int q = tid; q <= T; q += CTH) pJs[q] = q <= nJ ? pd[col0 + q] : 0.0;
+    for (int idx = tid; idx < T * CSTR; idx += CTH) {
+        (&DJt[0][0])[idx] = 0.0;
+        (&Xt[0][0])[idx] = 0.0;
+    }
+    __syncthreads();
+    // DJ[q][c], 1 <= q <= c < nJ, read row-major (coalesced).
+#pragma unroll 4
     for (int idx = tid; idx < T * T; idx += CTH) {
         const int qq = idx / T, c = idx % T;
         if (qq >= 1 && qq <= c && c < nJ)
-            DJs[qq][c] = fma((double)m[(size_t)(col0 + qq) * n + col0 + c], scale,
+            DJt[c][qq] = fma((double)m[(size_t)(col0 + qq) * n + col0 + c], scale,
                              (double)(T + qq - 1));
     }
     // Bulk result per cell: the minimum of P packed (cost << kbits | k)
@@ -307,7 +383,7 @@ __global__ __launch_bounds__(CTH) void k_close(int64_t *__restrict__ m, int32_t 
         const int idx = tid + CTH * u;
         const int rr = idx / T, c = idx % T;
         if (c < nJ) {
-            Xs[rr][c] = fma((double)(int64_t)(key[u] >> kbits), scale, (double)(T - 1));
+            Xt[c][rr] = fma((double)(int64_t)(key[u] >> kbits), scale, (double)(T - 1));
             Ks[rr][c] = (int32_t)(key[u] & kmask);
         }
     }
@@ -316,30 +392,35 @@ __global__ __launch_bounds__(CTH) void k_close(int64_t *__restrict__ m, int32_t 
     const int wmax = (T - 1) + (nJ - 1);
     for (int w = 0; w <= wmax; ++w) {
         const int c = w - (T - 1 - r);
-        if (c >= 0 && c < nJ) {  // uniform across the row group
-            const double PJ = pi_s * pJs[c + 1];
-            double best = __builtin_inf();
-#pragma unroll
-            for (int t = 0; t < CS; ++t) {
-                const int q = t * CG + g;
-                if (q >= r && q <= T - 2)
-                    best = fmin(best, fma(PJ, pIr[t], DIr[t]) + Xs[q + 1][c]);
-                if (q < c)
-                    best = fmin(best, fma(PJ, pJr[t], DJs[q + 1][c]) + Xrow[t]);
+        const int c_lo = w - (T - 1 - CROWS * h);  // c of the wave's first row
+        const int c_hi = c_lo + CROWS - 1;         // ... and of its last row
+        if (c_hi >= 0 && c_lo < nJ) {              // wave-uniform
+            const int cc = min(max(c, 0), nJ - 1);
+            const double pJc = pJs[cc + 1];
+            const double xbulk = Xt[cc][r];
+            double best;
+            switch (h) {
+            case 0: best = close_step<0>(R, Xt, DJt, cc, g, pJc); break;
+            case 1: best = close_step<1>(R, Xt, DJt, cc, g, pJc); break;
+            case 2: best = close_step<2>(R, Xt, DJt, cc, g, pJc); break;
+            case 3: best = close_step<3>(R, Xt, DJt, cc, g, pJc); break;
+            case 4: best = close_step<4>(R, Xt, DJt, cc, g, pJc); break;
+            case 5: best = close_step<5>(R, Xt, DJt, cc, g, pJc); break;
+            case 6: best = close_step<6>(R, Xt, DJt, cc, g, pJc); break;
+            default: best = close_step<7>(R, Xt, DJt, cc, g, pJc); break;
             }
-            best = fmin(best, __shfl_xor(best, 1, CG));
-            best = fmin(best, __shfl_xor(best, 2, CG));
-            best = fmin(best, __shfl_xor(best, 4, CG));
-            const double fin = fmin(best, Xs[r][c]);
+            const double fin = fmin(best, xbulk);
             const double cost = floor(fin * inv_scale);
             const double xv = cost * scale;
-            const int kl = (int)fma(-cost, scale, fin);
+            if (c >= 0 && c < nJ) {
 #pragma unroll
-            for (int t = 0; t < CS; ++t)
-                if (t * CG + g == c) Xrow[t] = xv;
-            if (g == 0) {
-                Xs[r][c] = xv;
-                if (kl != T - 1) Ks[r][c] = kl < T - 1 ? row0 + kl : col0 + (kl - T);
+                for (int t = 0; t < CS; ++t)
+                    if (t * CG + g == c) R.Xrow[t] = xv;
+                if (g == 0) {
+                    Xt[c][r] = xv;
+                    const int kl = (int)fma(-cost, scale, fin);
+                    if (kl != T - 1) Ks[r][c] = kl < T - 1 ? row0 + kl : col0 + (kl - T);
+                }
             }
         }
         __syncthreads();
@@ -349,7 +430,7 @@ __global__ __launch_bounds__(CTH) void k_close(int64_t *__restrict__ m, int32_t 
         const int rr = idx / T, c = idx % T;
         if (c < nJ) {
             const size_t o = (size_t)(row0 + rr) * n + col0 + c;
-            m[o] = (int64_t)(Xs[rr][c] * inv_scale);
+            m[o] = (int64_t)(Xt[c][rr] * inv_scale);
             s[o] = Ks[rr][c];
         }
     }
@@ -357,7 +438,7 @@ __global__ __launch_bounds__(CTH) void k_close(int64_t *__restrict__ m, int32_t 
         const int c = idx / T, rr = idx % T;
         if (c < nJ) {
             const size_t o = (size_t)(col0 + c) * n + row0 + rr;
-            m[o] = (int64_t)(Xs[rr][c] * inv_scale);
+            m[o] = (int64_t)(Xt[c][rr] * inv_scale);
             s[o] = -1;
         }
     }
