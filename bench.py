@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark of the matrix-chain-multiplication table fill on one MI355X.
+
+One step = one complete solve (m and s tables, every kernel of the path)
+of the synthetic n = 8192 chain (dims uniform in [1, 1024], seed 2), with
+the chain already resident in device memory and the output tables
+preallocated.  Prints one JSON line:
+
+  value      split evaluations per second, (n^3 - n)/6 per step
+  roofline   the bulk kernel (the dominant one) against the fp64 VALU issue
+             rate: each split evaluation is an fp64 fma, add and min, i.e.
+             3 VALU lane-ops; peak = 256 CUs x 64 lanes x 2.4 GHz.  Its
+             duration is measured with HIP events on the launch stream
+             during the timed steps.  `traffic` comes from the committed
+             rocprofv3 FETCH_SIZE/WRITE_SIZE summary, and is null when the
+             kernel source changed since it was taken.
+  cpu_baseline  the CPU oracle on a bounded window of the same chain.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MCM split evals/s at n=8192; batched instances/s + p99 latency vs plain"
+UNIT = "split evals/s"
+PEAK_OPS = 256 * 64 * 2.4e9      # fp64 VALU lane-ops per second
+OPS_PER_EVAL = 3                 # fma + add + min
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bulk_n8192_hbm_traffic.txt")
+TILED_SRC = os.path.join(ROOT, "paper_2008_01938_amd", "csrc", "k_tiled.hip")
+
+WORKLOADS = {
+    "mcm_single_n8192": ("single_n8192", "n=8192, dims uniform int32 [1,1024], seed 2"),
+    "mcm_single_n2048": ("single_n2048", "n=2048, dims uniform int32 [1,1024], seed 1"),
+    "mcm_single_n128": ("single_n128", "n=128, dims uniform int32 [1,64], seed 0"),
+}
+
+
+def source_sha() -> str:
+    with open(TILED_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def read_traffic():
+    """HBM bytes per bulk launch from the committed counter summary, or None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != source_sha():
+        return None
+    try:
+        return float(kv["bulk_hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def host_threads() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_baseline(p, target_s: float):
+    """Time the oracle on a window p[0:L+1] of the chain, L sized so the
+    run takes about target_s seconds of wall time on all host threads."""
+    import oracle
+    threads = host_threads()
+    n = len(p) - 1
+    L = min(1024, n)
+    t0 = time.perf_counter()
+    oracle.fill(p[:L + 1], threads=threads)
+    dt = time.perf_counter() - t0
+    rate = (L ** 3 - L) / 6 / max(dt, 1e-9)
+    want = int((6 * rate * target_s) ** (1 / 3))
+    L = max(L, min(n, want))
+    t0 = time.perf_counter()
+    oracle.fill(p[:L + 1], threads=threads)
+    dt = time.perf_counter() - t0
+    evals = (L ** 3 - L) / 6
+    return {"value": evals / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": f"oracle on the window of the first {L} matrices of the benchmark "
+                      f"chain ({evals:.3g} split evals, {dt:.1f} s wall, OpenMP over the "
+                      f"cells of each diagonal)"}
+
+
+def traffic_probe(binding, torch, chain, m, s):
+    """One solve, then a plain device copy of a known size, for counter
+    collection under rocprofv3 --pmc (FETCH_SIZE / WRITE_SIZE)."""
+    chain.solve_into(m, s)
+    torch.cuda.synchronize()
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"traffic_probe": True, "copy_bytes": nbytes,
+                      "kernel_source_sha256": source_sha()}), flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="mcm_single_n8192", choices=sorted(WORKLOADS))
+    ap.add_argument("--algo", default="auto", choices=["auto", "tiled", "wavefront"])
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="wall time target of the CPU-baseline sample (0 = skip)")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="one solve plus a 1 GiB copy, for rocprofv3 --pmc runs")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver is a "
+              "single-device library and multi-GPU runs are not part of this build.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np  # noqa: F401
+    import torch
+
+    from paper_2008_01938_amd import binding, workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+    binding.load()
+
+    maker, desc = WORKLOADS[args.workload]
+    p = getattr(workloads, maker)()
+    n = len(p) - 1
+    algo = args.algo
+    chosen = {binding.ALGO_TILED: "tiled", binding.ALGO_WAVEFRONT: "wavefront"}[
+        binding.select_algo(p) if algo == "auto" else binding.ALGOS[algo]]
+
+    chain = binding.Chain(p)
+    m = torch.empty((n, n), dtype=torch.int64, device="cuda")
+    s = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+
+    if args.traffic_probe:
+        traffic_probe(binding, torch, chain, m, s)
+        return 0
+
+    for _ in range(args.warmup):
+        chain.solve_into(m, s, algo=algo)
+    torch.cuda.synchronize()
+
+    binding.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        chain.solve_into(m, s, algo=algo)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {name: binding.profile_read(c) for c, name in
+            enumerate(["setup", "bulk", "close", "wavefront", "batched"])}
+    binding.profile_enable(False)
+
+    elapsed = t1 - t0
+    evals = (n ** 3 - n) / 6
+    value = evals * args.steps / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    dom = "bulk" if chosen == "tiled" else "wavefront"
+    d = prof[dom]
+    avg_s = d["ms"] / 1e3 / max(1, d["launches"])
+    evals_per_launch = d["split_evals"] / max(1, d["launches"])
+    achieved = evals_per_launch * OPS_PER_EVAL / avg_s if avg_s > 0 else 0.0
+    traffic = read_traffic() if chosen == "tiled" and args.workload == "mcm_single_n8192" else None
+    roofline = {
+        "bound": "alu",
+        "achieved": round(achieved / 1e12, 4),
+        "peak": round(PEAK_OPS / 1e12, 4),
+        "unit": "TOP/s",
+        "frac": round(achieved / PEAK_OPS, 4),
+        "traffic": traffic,
+        "kernel": "k_bulk" if dom == "bulk" else "k_wave_diag",
+        "ops_per_split_eval": OPS_PER_EVAL,
+        "avg_launch_ms": round(avg_s * 1e3, 5),
+        "launches_per_step": d["launches"] / args.steps,
+    }
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "dims": desc, "algo": chosen,
+                   "exact_integer": True, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in prof.items()},
+    }
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    chain.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -70,7 +70,7 @@ typedef enum mcm_status {
  *                       a register microtile; split range spread over
  *                       workgroups; a per-tile closure pass in LDS.  Exact
  *                       integers carried in fp64; accepts inputs with
- *                       (n-1) * max(p)^3 < 2^44 (else MCM_ERR_UNSUPPORTED).
+ *                       (n-1) * max(p)^3 < 2^46 (else MCM_ERR_UNSUPPORTED).
  */
 typedef enum mcm_algo {
     MCM_ALGO_AUTO = 0,
@@ -114,6 +114,29 @@ mcm_status mcm_solve(const int32_t *p, int32_t n, int64_t *m_out, int32_t *s_out
  * unknown algo. */
 mcm_status mcm_solve_algo(const int32_t *p, int32_t n, int64_t *m_out, int32_t *s_out,
                           int32_t algo, hipStream_t stream);
+
+/*
+ * Device-resident chain: validated once, dimensions copied to device
+ * memory, then solved any number of times without touching the host p.
+ *   mcm_chain_create  validates p (host, n+1 entries, read before return)
+ *                     and enqueues its upload on `stream`; *out receives an
+ *                     opaque handle owned by the caller.  Same status codes
+ *                     as mcm_check_chain, plus MCM_ERR_NO_MEMORY /
+ *                     MCM_ERR_DEVICE.
+ *   mcm_chain_solve   mcm_solve_algo on a created chain (m_out and s_out as
+ *                     in mcm_solve).  `stream` must be the creation stream or
+ *                     one ordered after it.
+ *   mcm_chain_n       number of matrices of the chain (0 for NULL).
+ *   mcm_chain_destroy releases the handle; its device memory is freed
+ *                     stream-ordered on `stream`, after work already
+ *                     enqueued there.  NULL is ignored.
+ */
+typedef struct mcm_chain mcm_chain;
+mcm_status mcm_chain_create(const int32_t *p, int32_t n, hipStream_t stream, mcm_chain **out);
+mcm_status mcm_chain_solve(const mcm_chain *chain, int32_t algo, int64_t *m_out, int32_t *s_out,
+                           hipStream_t stream);
+int32_t mcm_chain_n(const mcm_chain *chain);
+void mcm_chain_destroy(mcm_chain *chain, hipStream_t stream);
 
 /*
  * Kernel-level profiling on the library's own launches (HIP events on the

@@ -10,7 +10,7 @@ Importing the package loads nothing; the library is loaded on first use.
 """
 from __future__ import annotations
 
-__all__ = ["solve", "solve_into", "check_chain", "select_algo", "MCMError",
+__all__ = ["solve", "solve_into", "check_chain", "select_algo", "MCMError", "Chain",
            "profile_enable", "profile_read", "ALGOS"]
 
 

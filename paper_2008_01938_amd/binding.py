@@ -32,7 +32,8 @@ PROF_SETUP, PROF_BULK, PROF_CLOSE, PROF_WAVE, PROF_BATCH = range(5)
 # Every symbol include/mcm.h declares.
 EXPORTED = (
     "mcm_status_string", "mcm_version", "mcm_check_chain", "mcm_select_algo",
-    "mcm_solve", "mcm_solve_algo", "mcm_profile_enable", "mcm_profile_read",
+    "mcm_solve", "mcm_solve_algo", "mcm_chain_create", "mcm_chain_solve", "mcm_chain_n",
+    "mcm_chain_destroy", "mcm_profile_enable", "mcm_profile_read",
 )
 
 
@@ -76,6 +77,14 @@ def load() -> ctypes.CDLL:
             lib.mcm_solve.restype = ctypes.c_int
             lib.mcm_solve_algo.argtypes = [i32p, ctypes.c_int32, vp, vp, ctypes.c_int32, vp]
             lib.mcm_solve_algo.restype = ctypes.c_int
+            lib.mcm_chain_create.argtypes = [i32p, ctypes.c_int32, vp, ctypes.POINTER(vp)]
+            lib.mcm_chain_create.restype = ctypes.c_int
+            lib.mcm_chain_solve.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
+            lib.mcm_chain_solve.restype = ctypes.c_int
+            lib.mcm_chain_n.argtypes = [vp]
+            lib.mcm_chain_n.restype = ctypes.c_int32
+            lib.mcm_chain_destroy.argtypes = [vp, vp]
+            lib.mcm_chain_destroy.restype = None
             lib.mcm_profile_enable.argtypes = [ctypes.c_int32]
             lib.mcm_profile_enable.restype = None
             lib.mcm_profile_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -158,6 +167,42 @@ def solve(p, algo: int | str = ALGO_AUTO, device="cuda", stream=None):
     s = torch.empty((max(n, 0), max(n, 0)), dtype=torch.int32, device=device)
     solve_into(a, m, s, algo=algo, stream=stream)
     return m, s
+
+
+class Chain:
+    """A validated chain whose dimensions live in device memory
+    (mcm_chain_create); solve it repeatedly with :meth:`solve_into`."""
+
+    def __init__(self, p, stream=None):
+        a = _dims(p)
+        self.n = a.size - 1
+        h = ctypes.c_void_p()
+        st = load().mcm_chain_create(_p_ptr(a), self.n, ctypes.c_void_p(_stream_handle(stream)),
+                                     ctypes.byref(h))
+        if st != OK:
+            raise MCMError(st, "mcm_chain_create")
+        self._h = h
+
+    def solve_into(self, m, s, algo: int | str = ALGO_AUTO, stream=None) -> None:
+        import torch
+        if isinstance(algo, str):
+            algo = ALGOS[algo]
+        n = self.n
+        if not (m.is_cuda and s.is_cuda and m.dtype == torch.int64 and s.dtype == torch.int32):
+            raise TypeError("m must be a CUDA int64 tensor and s a CUDA int32 tensor")
+        if not (m.is_contiguous() and s.is_contiguous()) or m.numel() < n * n or \
+                s.numel() < n * n:
+            raise ValueError("m and s must be contiguous with at least n*n elements")
+        st = load().mcm_chain_solve(self._h, int(algo), ctypes.c_void_p(m.data_ptr()),
+                                    ctypes.c_void_p(s.data_ptr()),
+                                    ctypes.c_void_p(_stream_handle(stream)))
+        if st != OK:
+            raise MCMError(st, "mcm_chain_solve")
+
+    def close(self, stream=None) -> None:
+        if self._h:
+            load().mcm_chain_destroy(self._h, ctypes.c_void_p(_stream_handle(stream)))
+            self._h = None
 
 
 def profile_enable(on: bool = True) -> None:

@@ -258,29 +258,94 @@ int32_t mcm_select_algo(const int32_t *p, int32_t n)
     return tiled_accepts(ci) ? MCM_ALGO_TILED : MCM_ALGO_WAVEFRONT;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Host-side argument checks shared by the solve entry points; no HIP call.
+mcm_status check_outputs(const ChainInfo &ci, int64_t *m_out, int32_t *s_out, int32_t *algo)
+{
+    if (m_out == nullptr || s_out == nullptr) return MCM_ERR_INVALID_ARG;
+    if (((uintptr_t)m_out & 7) != 0 || ((uintptr_t)s_out & 3) != 0) return MCM_ERR_INVALID_ARG;
+    if (*algo == MCM_ALGO_AUTO) *algo = tiled_accepts(ci) ? MCM_ALGO_TILED : MCM_ALGO_WAVEFRONT;
+    if (*algo != MCM_ALGO_WAVEFRONT && *algo != MCM_ALGO_TILED) return MCM_ERR_INVALID_ARG;
+    if (*algo == MCM_ALGO_TILED && !tiled_accepts(ci)) return MCM_ERR_UNSUPPORTED;
+    return MCM_OK;
+}
+
+mcm_status run_algo(const DeviceChain &dc, const ChainInfo &ci, int32_t algo, int64_t *m_out,
+                    int32_t *s_out, hipStream_t stream)
+{
+    if (algo == MCM_ALGO_TILED) return run_tiled(dc, ci, m_out, s_out, stream);
+    return run_wavefront(dc, ci, m_out, s_out, stream);
+}
+
+}  // namespace
+
+struct mcm_chain {
+    ChainInfo ci;
+    DeviceChain dc;
+    void *block = nullptr;
+};
+
+extern "C" {
+
 mcm_status mcm_solve_algo(const int32_t *p, int32_t n, int64_t *m_out, int32_t *s_out,
                           int32_t algo, hipStream_t stream)
 {
     ChainInfo ci;
     mcm_status st = check_chain(p, n, &ci);
     if (st != MCM_OK) return st;
-    if (m_out == nullptr || s_out == nullptr) return MCM_ERR_INVALID_ARG;
-    if (((uintptr_t)m_out & 7) != 0 || ((uintptr_t)s_out & 3) != 0) return MCM_ERR_INVALID_ARG;
-    if (algo == MCM_ALGO_AUTO) algo = tiled_accepts(ci) ? MCM_ALGO_TILED : MCM_ALGO_WAVEFRONT;
-    if (algo != MCM_ALGO_WAVEFRONT && algo != MCM_ALGO_TILED) return MCM_ERR_INVALID_ARG;
-    if (algo == MCM_ALGO_TILED && !tiled_accepts(ci)) return MCM_ERR_UNSUPPORTED;
+    st = check_outputs(ci, m_out, s_out, &algo);
+    if (st != MCM_OK) return st;
 
     if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
     void *chain_block = nullptr;
     DeviceChain dc;
     st = upload_chain(p, n, stream, &chain_block, &dc);
     if (st != MCM_OK) return st;
-    if (algo == MCM_ALGO_TILED)
-        st = run_tiled(dc, ci, m_out, s_out, stream);
-    else
-        st = run_wavefront(dc, ci, m_out, s_out, stream);
+    st = run_algo(dc, ci, algo, m_out, s_out, stream);
     ws_free(chain_block, stream);
     return st;
+}
+
+mcm_status mcm_chain_create(const int32_t *p, int32_t n, hipStream_t stream, mcm_chain **out)
+{
+    if (out == nullptr) return MCM_ERR_INVALID_ARG;
+    *out = nullptr;
+    ChainInfo ci;
+    mcm_status st = check_chain(p, n, &ci);
+    if (st != MCM_OK) return st;
+    if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
+    mcm_chain *c = new (std::nothrow) mcm_chain;
+    if (!c) return MCM_ERR_NO_MEMORY;
+    c->ci = ci;
+    st = upload_chain(p, n, stream, &c->block, &c->dc);
+    if (st != MCM_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return MCM_OK;
+}
+
+mcm_status mcm_chain_solve(const mcm_chain *chain, int32_t algo, int64_t *m_out, int32_t *s_out,
+                           hipStream_t stream)
+{
+    if (chain == nullptr) return MCM_ERR_INVALID_ARG;
+    mcm_status st = check_outputs(chain->ci, m_out, s_out, &algo);
+    if (st != MCM_OK) return st;
+    if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
+    return run_algo(chain->dc, chain->ci, algo, m_out, s_out, stream);
+}
+
+int32_t mcm_chain_n(const mcm_chain *chain) { return chain ? chain->ci.n : 0; }
+
+void mcm_chain_destroy(mcm_chain *chain, hipStream_t stream)
+{
+    if (!chain) return;
+    ws_free(chain->block, stream);
+    delete chain;
 }
 
 mcm_status mcm_solve(const int32_t *p, int32_t n, int64_t *m_out, int32_t *s_out,

@@ -93,3 +93,27 @@ def test_profile_read_rejects_bad_class(lib):
     n = ctypes.c_int64()
     assert lib.mcm_profile_read(99, ctypes.byref(d), ctypes.byref(n), ctypes.byref(d)) == \
         binding.ERR_INVALID_ARG
+
+
+def test_bench_refuses_multi_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_chain_create_rejects_bad_input(lib):
+    h = ctypes.c_void_p()
+    bad = np.array([3, 0, 4], dtype=np.int32)
+    st = lib.mcm_chain_create(bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 2,
+                              ctypes.c_void_p(0), ctypes.byref(h))
+    assert st == binding.ERR_INVALID_ARG and not h.value
+    assert lib.mcm_chain_n(None) == 0
+    lib.mcm_chain_destroy(None, ctypes.c_void_p(0))   # NULL is ignored
+    m = np.zeros(4, dtype=np.int64)
+    s = np.zeros(4, dtype=np.int32)
+    assert lib.mcm_chain_solve(None, 0, ctypes.c_void_p(m.ctypes.data),
+                               ctypes.c_void_p(s.ctypes.data), ctypes.c_void_p(0)) == \
+        binding.ERR_INVALID_ARG

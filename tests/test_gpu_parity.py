@@ -208,3 +208,22 @@ def test_n8192_all_equal_closed_form():
     assert np.array_equal(m[iu, ju], (ju - iu).astype(np.int64) * d ** 3)
     assert np.array_equal(s[iu, ju], iu.astype(np.int32))
     assert m[0, n - 1] == 8795019280384
+
+
+def test_chain_api_matches_solve():
+    import torch
+    p = workloads.uniform_dims(333, 1, 1024, 4242)
+    n = len(p) - 1
+    _say("[gpu] chain api n=333")
+    ch = binding.Chain(p)
+    m = torch.empty((n, n), dtype=torch.int64, device="cuda")
+    s = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    for algo in ("tiled", "wavefront", "auto"):
+        m.fill_(-7)
+        s.fill_(-7)
+        ch.solve_into(m, s, algo=algo)
+        torch.cuda.synchronize()
+        om, os_ = oracle.fill(p, threads=oracle.default_threads())
+        assert np.array_equal(m.cpu().numpy(), om) and np.array_equal(s.cpu().numpy(), os_)
+    ch.close()
+    torch.cuda.synchronize()
