@@ -116,6 +116,29 @@ mcm_status mcm_solve_algo(const int32_t *p, int32_t n, int64_t *m_out, int32_t *
                           int32_t algo, hipStream_t stream);
 
 /*
+ * Many independent chains in one call.  All chains advance together, one
+ * tile-diagonal per iteration, each kernel launch serving every chain that
+ * is still active, so a batch of thousands of small chains costs a few
+ * dozen launches instead of thousands.  Chains outside the fp64-exact range
+ * of the tiled path are solved with the int64 wavefront.
+ *   count   number of chains (>= 0; 0 is a no-op).
+ *   n       host, count entries: matrices of chain b (>= 1).
+ *   p_off   host, count entries: chain b's dims are p_all[p_off[b] ..
+ *           p_off[b] + n[b]] (offsets may overlap; >= 0).
+ *   p_all   host, dims of all chains (read before return).
+ *   tab_off host, count entries: chain b's m table is m_all + tab_off[b]
+ *           and its s table s_all + tab_off[b], n[b]*n[b] elements each,
+ *           row-major, same contract as mcm_solve; tables of different
+ *           chains must not overlap.
+ *   m_all, s_all  device buffers (int64 / int32), caller-owned.
+ * Every chain is validated before anything is enqueued; the first failure
+ * is returned and nothing runs.
+ */
+mcm_status mcm_solve_batched(int32_t count, const int32_t *n, const int64_t *p_off,
+                             const int32_t *p_all, const int64_t *tab_off, int64_t *m_all,
+                             int32_t *s_all, hipStream_t stream);
+
+/*
  * Device-resident chain: validated once, dimensions copied to device
  * memory, then solved any number of times without touching the host p.
  *   mcm_chain_create  validates p (host, n+1 entries, read before return)

@@ -32,7 +32,7 @@ PROF_SETUP, PROF_BULK, PROF_CLOSE, PROF_WAVE, PROF_BATCH = range(5)
 # Every symbol include/mcm.h declares.
 EXPORTED = (
     "mcm_status_string", "mcm_version", "mcm_check_chain", "mcm_select_algo",
-    "mcm_solve", "mcm_solve_algo", "mcm_chain_create", "mcm_chain_solve", "mcm_chain_n",
+    "mcm_solve", "mcm_solve_algo", "mcm_solve_batched", "mcm_chain_create", "mcm_chain_solve", "mcm_chain_n",
     "mcm_chain_destroy", "mcm_profile_enable", "mcm_profile_read",
 )
 
@@ -77,6 +77,9 @@ def load() -> ctypes.CDLL:
             lib.mcm_solve.restype = ctypes.c_int
             lib.mcm_solve_algo.argtypes = [i32p, ctypes.c_int32, vp, vp, ctypes.c_int32, vp]
             lib.mcm_solve_algo.restype = ctypes.c_int
+            i64p = ctypes.POINTER(ctypes.c_int64)
+            lib.mcm_solve_batched.argtypes = [ctypes.c_int32, i32p, i64p, i32p, i64p, vp, vp, vp]
+            lib.mcm_solve_batched.restype = ctypes.c_int
             lib.mcm_chain_create.argtypes = [i32p, ctypes.c_int32, vp, ctypes.POINTER(vp)]
             lib.mcm_chain_create.restype = ctypes.c_int
             lib.mcm_chain_solve.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
@@ -167,6 +170,48 @@ def solve(p, algo: int | str = ALGO_AUTO, device="cuda", stream=None):
     s = torch.empty((max(n, 0), max(n, 0)), dtype=torch.int32, device=device)
     solve_into(a, m, s, algo=algo, stream=stream)
     return m, s
+
+
+def solve_batched_into(ns, p_off, p_all, tab_off, m_all, s_all, stream=None) -> None:
+    """Enqueue mcm_solve_batched: chain b has ns[b] matrices, dims
+    p_all[p_off[b] : p_off[b] + ns[b] + 1], and writes its n*n tables at
+    element offset tab_off[b] of the flat device tensors m_all (int64) and
+    s_all (int32)."""
+    import torch
+    ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
+    p_off = np.ascontiguousarray(np.asarray(p_off, dtype=np.int64))
+    p_all = np.ascontiguousarray(np.asarray(p_all, dtype=np.int32))
+    tab_off = np.ascontiguousarray(np.asarray(tab_off, dtype=np.int64))
+    count = ns.size
+    if not (p_off.size == count and tab_off.size == count):
+        raise ValueError("ns, p_off and tab_off must have one entry per chain")
+    if not (m_all.is_cuda and s_all.is_cuda and m_all.dtype == torch.int64 and
+            s_all.dtype == torch.int32 and m_all.is_contiguous() and s_all.is_contiguous()):
+        raise TypeError("m_all / s_all must be contiguous CUDA int64 / int32 tensors")
+    if count:
+        if np.any(ns < 1) or np.any(p_off < 0) or np.any(tab_off < 0):
+            raise ValueError("n >= 1 and non-negative offsets required")
+        if int(np.max(p_off + ns + 1)) > p_all.size:
+            raise ValueError("p_all too short for the given offsets")
+        need = int(np.max(tab_off + ns.astype(np.int64) ** 2))
+        if m_all.numel() < need or s_all.numel() < need:
+            raise ValueError("m_all / s_all too small for the given table offsets")
+    i64 = ctypes.POINTER(ctypes.c_int64)
+    st = load().mcm_solve_batched(count, _p_ptr(ns), p_off.ctypes.data_as(i64), _p_ptr(p_all),
+                                  tab_off.ctypes.data_as(i64), ctypes.c_void_p(m_all.data_ptr()),
+                                  ctypes.c_void_p(s_all.data_ptr()),
+                                  ctypes.c_void_p(_stream_handle(stream)))
+    if st != OK:
+        raise MCMError(st, "mcm_solve_batched")
+
+
+def table_offsets(ns) -> np.ndarray:
+    """Packed element offsets of n*n tables, one after another."""
+    ns = np.asarray(ns, dtype=np.int64)
+    off = np.zeros(ns.size, dtype=np.int64)
+    if ns.size > 1:
+        off[1:] = np.cumsum(ns[:-1] ** 2)
+    return off
 
 
 class Chain:

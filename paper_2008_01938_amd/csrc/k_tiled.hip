@@ -34,6 +34,7 @@
 // among equal costs, the smallest k_local -- the smallest k when k_local
 // increases with k.  A split evaluation is fma + add + min.
 #include <math.h>
+#include <string.h>
 
 #include "mcm_internal.h"
 
@@ -45,19 +46,43 @@ constexpr int KC = 16;       // k values staged per LDS round in k_bulk
 constexpr int NTH = 256;     // threads per workgroup
 constexpr double kPad = 4611686018427387904.0;  // 2^62: never wins a min
 
+// The segment of a launch that workgroup b belongs to (segments are sorted
+// by their first workgroup; every thread of the workgroup agrees).
+__device__ __forceinline__ int find_seg(const TileSeg *__restrict__ seg, int nseg, int b)
+{
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg[mid].first <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 // ------------------------------------------------------------------------
 // Diagonal tiles (I, I): every split of a cell inside the tile uses two
 // cells of the same tile.  Local diagonals dd = 1..nI-1 in order; four
 // lanes per cell, lexicographic (cost, k) reduction.  int64 arithmetic.
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(NTH) void k_tri(const int32_t *__restrict__ p, int32_t n,
-                                             int64_t *__restrict__ m, int32_t *__restrict__ s)
+__global__ __launch_bounds__(NTH) void k_tri(const TileChain *__restrict__ chains,
+                                             const TileSeg *__restrict__ segs, int nseg,
+                                             const int32_t *__restrict__ p_all,
+                                             int64_t *__restrict__ m_all,
+                                             int32_t *__restrict__ s_all)
 {
     __shared__ int64_t tv[T][T + 1];
     __shared__ int32_t sv[T][T + 1];
     __shared__ int64_t ps[T + 1];
     const int tid = threadIdx.x;
-    const int base = blockIdx.x * T;
+    const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
+    const TileChain ch = chains[sg.chain];
+    const int32_t n = ch.n;
+    const int32_t *__restrict__ p = p_all + ch.p_off;
+    int64_t *__restrict__ m = m_all + ch.m_off;
+    int32_t *__restrict__ s = s_all + ch.s_off;
+    const int base = (blockIdx.x - sg.first) * T;
     const int nI = min(T, n - base);
     for (int q = tid; q <= nI; q += NTH) ps[q] = p[base + q];
     for (int r = tid; r < T; r += NTH) tv[r][r] = 0;
@@ -109,18 +134,25 @@ __global__ __launch_bounds__(NTH) void k_tri(const int32_t *__restrict__ p, int3
 // (J = I + D) and chunk b % P of its bulk range.  Thread (tx, ty) owns the
 // cells rows ty + 16a, columns tx + 16b (a, b = 0..3) of the tile.
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(NTH) void k_bulk(const int64_t *__restrict__ m,
-                                              const double *__restrict__ pd, int32_t n,
-                                              int32_t D, int32_t KS, int32_t P, int32_t kb,
-                                              int32_t kbits, uint64_t *__restrict__ part)
+__global__ __launch_bounds__(NTH) void k_bulk(const TileChain *__restrict__ chains,
+                                              const TileSeg *__restrict__ segs, int nseg,
+                                              const int64_t *__restrict__ m_all,
+                                              const double *__restrict__ pd_all,
+                                              uint64_t *__restrict__ part_all)
 {
     __shared__ double As[2][KC][T + 1];  // As[kk][r] = m[row0+r][k] * 2^kb
     __shared__ double Bs[2][KC][T];      // Bs[kk][c] = m[k+1][col0+c] * 2^kb + (k - k0)
     __shared__ double Ps[2][KC];         // p[k+1]
 
     const int tid = threadIdx.x;
-    const int tile = blockIdx.x / P;
-    const int chunk = blockIdx.x - tile * P;
+    const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
+    const TileChain ch = chains[sg.chain];
+    const int32_t n = ch.n, D = sg.D, KS = sg.KS, P = sg.P, kb = ch.kb, kbits = ch.kbits;
+    const int64_t *__restrict__ m = m_all + ch.m_off;
+    const double *__restrict__ pd = pd_all + ch.p_off;
+    const int local = blockIdx.x - sg.first;
+    const int tile = local / P;
+    const int chunk = local - tile * P;
     const int I = tile, J = tile + D;
     const int row0 = I * T, col0 = J * T;
     const int k0 = (I + 1) * T - 1 + chunk * KS;
@@ -197,7 +229,7 @@ __global__ __launch_bounds__(NTH) void k_bulk(const int64_t *__restrict__ m,
         buf ^= 1;
     }
 
-    uint64_t *out = part + (size_t)blockIdx.x * T * T;
+    uint64_t *out = part_all + sg.part_off + (size_t)local * T * T;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
@@ -294,10 +326,12 @@ __device__ __forceinline__ double close_step(const CloseRegs &R, const double (*
     return min_group(v[0]);
 }
 
-__global__ __launch_bounds__(CTH) void k_close(int64_t *__restrict__ m, int32_t *__restrict__ s,
-                                               const double *__restrict__ pd, int32_t n,
-                                               int32_t D, int32_t P, int32_t kb, int32_t kbits,
-                                               const uint64_t *__restrict__ part)
+__global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ chains,
+                                               const TileSeg *__restrict__ segs, int nseg,
+                                               int64_t *__restrict__ m_all,
+                                               int32_t *__restrict__ s_all,
+                                               const double *__restrict__ pd_all,
+                                               const uint64_t *__restrict__ part_all)
 {
     // Column-major with a column stride of CSTR = 72 doubles.  LDS has 32
     // banks of 4 bytes, so a 64-bit read is conflict-free when the 16 lanes
@@ -312,7 +346,14 @@ __global__ __launch_bounds__(CTH) void k_close(int64_t *__restrict__ m, int32_t 
     __shared__ double pJs[T + 1];     // p[col0 + q]
 
     const int tid = threadIdx.x;
-    const int I = blockIdx.x, J = I + D;
+    const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
+    const TileChain ch = chains[sg.chain];
+    const int32_t n = ch.n, D = sg.D, P = sg.P, kb = ch.kb, kbits = ch.kbits;
+    int64_t *__restrict__ m = m_all + ch.m_off;
+    int32_t *__restrict__ s = s_all + ch.s_off;
+    const double *__restrict__ pd = pd_all + ch.p_off;
+    const uint64_t *__restrict__ part = part_all + sg.part_off;
+    const int I = blockIdx.x - sg.first, J = I + D;
     const int row0 = I * T, col0 = J * T;
     const int nJ = min(T, n - col0);
     const double scale = ldexp(1.0, kb);
@@ -444,18 +485,17 @@ __global__ __launch_bounds__(CTH) void k_close(int64_t *__restrict__ m, int32_t 
     }
 }
 
-struct Plan {
-    int32_t NT = 0, kb = 0, kbits = 0;
-};
-
 // Chunking of the bulk range of tile-diagonal D: P chunks of KS splits.
+// Aims at about 1024 workgroups per launch for a lone chain, at least 64
+// splits per chunk, at most 32 chunks per tile, and KS <= 2^kb so the fp64
+// key's split field holds every local index of a chunk.
 void bulk_split(int32_t NT, int32_t D, int32_t kb, int32_t *KS, int32_t *P)
 {
     const int32_t tiles = NT - D;
     const int32_t L = (D - 1) * T + 1;
     const int32_t target_groups = 1024;
     int32_t want = (target_groups + tiles - 1) / tiles;
-    int32_t maxp = (L + 63) / 64;  // at least 64 splits per chunk
+    int32_t maxp = (L + 63) / 64;
     if (maxp > 32) maxp = 32;
     if (want > maxp) want = maxp;
     if (want < 1) want = 1;
@@ -477,6 +517,17 @@ int32_t bitlen_u64(uint64_t v)
     return b;
 }
 
+// Split evaluations of one launch kind for chain c at tile-diagonal D.
+double tri_evals(int32_t n, int32_t NT)
+{
+    double ev = 0.0;
+    for (int32_t I = 0; I < NT; ++I) {
+        const double nI = (double)((n - I * T) < T ? (n - I * T) : T);
+        ev += (nI * nI * nI - nI) / 6.0;
+    }
+    return ev;
+}
+
 }  // namespace
 
 bool tiled_accepts(const ChainInfo &ci)
@@ -485,75 +536,162 @@ bool tiled_accepts(const ChainInfo &ci)
     return ci.cost_bits + 7 <= 53 && ci.cost_bits + kbits <= 64;
 }
 
+int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t s_off,
+                   int64_t p_off)
+{
+    TileChain c{};
+    c.m_off = m_off;
+    c.s_off = s_off;
+    c.p_off = p_off;
+    c.n = ci.n;
+    c.kb = 53 - ci.cost_bits;
+    if (c.kb > 20) c.kb = 20;
+    c.kbits = bitlen_u64((uint64_t)(ci.n > 1 ? ci.n - 1 : 1));
+    plan.chains.push_back(c);
+    plan.NT.push_back((ci.n + T - 1) / T);
+    return (int)plan.chains.size() - 1;
+}
+
+void plan_add_iteration(TiledPlan &plan, const std::vector<int> &chain_ids,
+                        const std::vector<int> &Ds)
+{
+    TiledLaunch tri{TK_TRI, (int)plan.segs.size(), 0, 0, 0.0};
+    for (size_t u = 0; u < chain_ids.size(); ++u) {
+        const int c = chain_ids[u];
+        if (Ds[u] != 0) continue;
+        TileSeg sg{};
+        sg.first = tri.blocks;
+        sg.chain = c;
+        sg.D = 0;
+        plan.segs.push_back(sg);
+        tri.nseg += 1;
+        tri.blocks += plan.NT[c];
+        tri.evals += tri_evals(plan.chains[c].n, plan.NT[c]);
+    }
+    if (tri.nseg) plan.launches.push_back(tri);
+
+    // Bulk and closure share each chain's partial buffer slice.
+    std::vector<int64_t> off(chain_ids.size(), 0);
+    std::vector<int32_t> KSv(chain_ids.size(), 0), Pv(chain_ids.size(), 0);
+    size_t used = 0;
+    for (size_t u = 0; u < chain_ids.size(); ++u) {
+        const int c = chain_ids[u], D = Ds[u];
+        if (D < 2 || D >= plan.NT[c]) continue;
+        bulk_split(plan.NT[c], D, plan.chains[c].kb, &KSv[u], &Pv[u]);
+        off[u] = (int64_t)used;
+        used += (size_t)(plan.NT[c] - D) * Pv[u] * T * T;
+    }
+    if (used > plan.part_elems) plan.part_elems = used;
+
+    TiledLaunch bulk{TK_BULK, (int)plan.segs.size(), 0, 0, 0.0};
+    for (size_t u = 0; u < chain_ids.size(); ++u) {
+        const int c = chain_ids[u], D = Ds[u];
+        if (D < 2 || D >= plan.NT[c]) continue;
+        const int32_t n = plan.chains[c].n, NT = plan.NT[c], tiles = NT - D;
+        TileSeg sg{};
+        sg.part_off = off[u];
+        sg.first = bulk.blocks;
+        sg.chain = c;
+        sg.D = D;
+        sg.P = Pv[u];
+        sg.KS = KSv[u];
+        plan.segs.push_back(sg);
+        bulk.nseg += 1;
+        bulk.blocks += tiles * Pv[u];
+        const int32_t nlast = n - (NT - 1) * T;
+        const double cells = (double)(tiles - 1) * T * T + (double)T * nlast;
+        bulk.evals += cells * ((double)(D - 1) * T + 1);
+    }
+    if (bulk.nseg) plan.launches.push_back(bulk);
+
+    TiledLaunch close{TK_CLOSE, (int)plan.segs.size(), 0, 0, 0.0};
+    for (size_t u = 0; u < chain_ids.size(); ++u) {
+        const int c = chain_ids[u], D = Ds[u];
+        if (D < 1 || D >= plan.NT[c]) continue;
+        const int32_t n = plan.chains[c].n, NT = plan.NT[c], tiles = NT - D;
+        TileSeg sg{};
+        sg.part_off = off[u];
+        sg.first = close.blocks;
+        sg.chain = c;
+        sg.D = D;
+        sg.P = Pv[u];
+        sg.KS = KSv[u];
+        plan.segs.push_back(sg);
+        close.nseg += 1;
+        close.blocks += tiles;
+        // (a) and (b) splits of every cell, plus the single bulk split of
+        // D == 1: per tile sum over cells of (T-1-r) + c.
+        const int32_t nlast = n - (NT - 1) * T;
+        const double per_full = (double)T * T * (T - 1);
+        const double per_last =
+            (double)nlast * T * (T - 1) / 2.0 + (double)T * nlast * (nlast - 1) / 2.0;
+        double ev = (double)(tiles - 1) * per_full + per_last;
+        if (D == 1) ev += (double)(tiles - 1) * T * T + (double)T * nlast;
+        close.evals += ev;
+    }
+    if (close.nseg) plan.launches.push_back(close);
+}
+
+mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double *pd,
+                          int64_t *m_all, int32_t *s_all, hipStream_t stream)
+{
+    if (plan.launches.empty()) return MCM_OK;
+    // One device block: chain table, then segment table.
+    const size_t cbytes = plan.chains.size() * sizeof(TileChain);
+    const size_t sbytes = plan.segs.size() * sizeof(TileSeg);
+    const size_t soff = (cbytes + 255) / 256 * 256;
+    void *tables = nullptr;
+    mcm_status st = upload_blob(stream, &tables, soff + sbytes,
+                                [&](char *dst) {
+                                    memcpy(dst, plan.chains.data(), cbytes);
+                                    memcpy(dst + soff, plan.segs.data(), sbytes);
+                                });
+    if (st != MCM_OK) return st;
+    const TileChain *chains = (const TileChain *)tables;
+    const TileSeg *segs = (const TileSeg *)((const char *)tables + soff);
+    uint64_t *part = nullptr;
+    if (plan.part_elems &&
+        ws_alloc((void **)&part, plan.part_elems * sizeof(uint64_t), stream) != hipSuccess) {
+        ws_free(tables, stream);
+        return MCM_ERR_NO_MEMORY;
+    }
+    for (const TiledLaunch &L : plan.launches) {
+        const TileSeg *sg = segs + L.seg_begin;
+        hipError_t e;
+        if (L.kind == TK_TRI) {
+            ProfileScope ps(KC_SETUP, stream, L.evals);
+            hipLaunchKernelGGL(k_tri, dim3(L.blocks), dim3(NTH), 0, stream, chains, sg, L.nseg,
+                               p, m_all, s_all);
+            e = hipGetLastError();
+        } else if (L.kind == TK_BULK) {
+            ProfileScope ps(KC_BULK, stream, L.evals);
+            hipLaunchKernelGGL(k_bulk, dim3(L.blocks), dim3(NTH), 0, stream, chains, sg, L.nseg,
+                               m_all, pd, part);
+            e = hipGetLastError();
+        } else {
+            ProfileScope ps(KC_CLOSE, stream, L.evals);
+            hipLaunchKernelGGL(k_close, dim3(L.blocks), dim3(CTH), 0, stream, chains, sg,
+                               L.nseg, m_all, s_all, pd, part);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) {
+            st = MCM_ERR_DEVICE;
+            break;
+        }
+    }
+    if (part) ws_free(part, stream);
+    ws_free(tables, stream);
+    return st;
+}
+
 mcm_status run_tiled(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int32_t *s,
                      hipStream_t stream)
 {
     if (!tiled_accepts(ci)) return MCM_ERR_UNSUPPORTED;
-    const int32_t n = ci.n;
-    Plan pl;
-    pl.NT = (n + T - 1) / T;
-    pl.kb = 53 - ci.cost_bits;
-    if (pl.kb > 20) pl.kb = 20;
-    pl.kbits = bitlen_u64((uint64_t)(n > 1 ? n - 1 : 1));
-
-    // Partial buffer: the largest tile-diagonal.
-    size_t part_elems = 0;
-    for (int32_t D = 2; D < pl.NT; ++D) {
-        int32_t KS, P;
-        bulk_split(pl.NT, D, pl.kb, &KS, &P);
-        const size_t e = (size_t)(pl.NT - D) * P * T * T;
-        if (e > part_elems) part_elems = e;
-    }
-    uint64_t *part = nullptr;
-    if (part_elems) {
-        if (ws_alloc((void **)&part, part_elems * sizeof(uint64_t), stream) != hipSuccess)
-            return MCM_ERR_NO_MEMORY;
-    }
-    mcm_status st = MCM_OK;
-    {
-        // Split evaluations inside the diagonal tiles: sum over tiles of
-        // (nI^3 - nI) / 6.
-        double ev = 0.0;
-        for (int32_t I = 0; I < pl.NT; ++I) {
-            const double nI = (double)((n - I * T) < T ? (n - I * T) : T);
-            ev += (nI * nI * nI - nI) / 6.0;
-        }
-        ProfileScope ps(KC_SETUP, stream, ev);
-        hipLaunchKernelGGL(k_tri, dim3(pl.NT), dim3(NTH), 0, stream, dc.p, n, m, s);
-        if (hipGetLastError() != hipSuccess) st = MCM_ERR_DEVICE;
-    }
-    for (int32_t D = 1; D < pl.NT && st == MCM_OK; ++D) {
-        const int32_t tiles = pl.NT - D;
-        const int32_t nlast = n - (pl.NT - 1) * T;  // valid columns of the last tile
-        const double cells = (double)(tiles - 1) * T * T + (double)T * nlast;
-        int32_t KS = 0, P = 0;
-        if (D >= 2) {
-            bulk_split(pl.NT, D, pl.kb, &KS, &P);
-            const double L = (double)(D - 1) * T + 1;
-            ProfileScope ps(KC_BULK, stream, cells * L);
-            hipLaunchKernelGGL(k_bulk, dim3(tiles * P), dim3(NTH), 0, stream, m, dc.pd, n, D, KS,
-                               P, pl.kb, pl.kbits, part);
-            if (hipGetLastError() != hipSuccess) {
-                st = MCM_ERR_DEVICE;
-                break;
-            }
-        }
-        {
-            // Closure evaluations: (a) and (b) splits, plus the single bulk
-            // split when D == 1.  Per tile: sum over cells of (T-1-r) + c.
-            const double per_full = (double)T * T * (T - 1);
-            const double per_last = (double)nlast * T * (T - 1) / 2.0 +
-                                    (double)T * nlast * (nlast - 1) / 2.0;
-            double ev = (double)(tiles - 1) * per_full + per_last;
-            if (D == 1) ev += cells;
-            ProfileScope ps(KC_CLOSE, stream, ev);
-            hipLaunchKernelGGL(k_close, dim3(tiles), dim3(CTH), 0, stream, m, s, dc.pd, n, D, P,
-                               pl.kb, pl.kbits, part);
-            if (hipGetLastError() != hipSuccess) st = MCM_ERR_DEVICE;
-        }
-    }
-    if (part) ws_free(part, stream);
-    return st;
+    TiledPlan plan;
+    const int c = plan_add_chain(plan, ci, 0, 0, 0);
+    for (int D = 0; D < plan.NT[c]; ++D) plan_add_iteration(plan, {c}, {D});
+    return run_tiled_plan(plan, dc.p, dc.pd, m, s, stream);
 }
 
 }  // namespace mcm

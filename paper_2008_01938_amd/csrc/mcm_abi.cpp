@@ -158,18 +158,34 @@ void prof_drain_locked()
 mcm_status upload_chain(const int32_t *p, int32_t n, hipStream_t stream, void **dev_block,
                         DeviceChain *dc)
 {
-    int device = 0;
-    if (hipGetDevice(&device) != hipSuccess) return MCM_ERR_DEVICE;
-    pool_setup(device);
     // Layout: n+1 int32 (padded to 8 bytes), then n+1 doubles.
     const size_t np = (size_t)n + 1;
     const size_t off_d = (np * sizeof(int32_t) + 7) / 8 * 8;
     const size_t bytes = off_d + np * sizeof(double);
+    void *dev = nullptr;
+    mcm_status st = upload_blob(stream, &dev, bytes, [&](char *h) {
+        memcpy(h, p, np * sizeof(int32_t));
+        double *hd = (double *)(h + off_d);
+        for (size_t t = 0; t < np; ++t) hd[t] = (double)p[t];
+    });
+    if (st != MCM_OK) return st;
+    *dev_block = dev;
+    dc->p = (const int32_t *)dev;
+    dc->pd = (const double *)((char *)dev + off_d);
+    return MCM_OK;
+}
+
+}  // namespace
+
+mcm_status upload_blob(hipStream_t stream, void **dev_out, size_t bytes,
+                       const std::function<void(char *)> &fill)
+{
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return MCM_ERR_DEVICE;
+    pool_setup(device);
     StagingBuf *sb = stage_acquire(bytes, device);
     if (!sb) return MCM_ERR_NO_MEMORY;
-    memcpy(sb->host, p, np * sizeof(int32_t));
-    double *hd = (double *)((char *)sb->host + off_d);
-    for (size_t t = 0; t < np; ++t) hd[t] = (double)p[t];
+    fill((char *)sb->host);
     void *dev = nullptr;
     if (ws_alloc(&dev, bytes, stream) != hipSuccess) {
         stage_release(sb);
@@ -182,13 +198,9 @@ mcm_status upload_chain(const int32_t *p, int32_t n, hipStream_t stream, void **
         ws_free(dev, stream);
         return MCM_ERR_DEVICE;
     }
-    *dev_block = dev;
-    dc->p = (const int32_t *)dev;
-    dc->pd = (const double *)((char *)dev + off_d);
+    *dev_out = dev;
     return MCM_OK;
 }
-
-}  // namespace
 
 hipError_t ws_alloc(void **ptr, size_t bytes, hipStream_t stream)
 {
@@ -306,6 +318,59 @@ mcm_status mcm_solve_algo(const int32_t *p, int32_t n, int64_t *m_out, int32_t *
     if (st != MCM_OK) return st;
     st = run_algo(dc, ci, algo, m_out, s_out, stream);
     ws_free(chain_block, stream);
+    return st;
+}
+
+mcm_status mcm_solve_batched(int32_t count, const int32_t *n, const int64_t *p_off,
+                             const int32_t *p_all, const int64_t *tab_off, int64_t *m_all,
+                             int32_t *s_all, hipStream_t stream)
+{
+    if (count < 0) return MCM_ERR_INVALID_ARG;
+    if (count == 0) return MCM_OK;
+    if (!n || !p_off || !p_all || !tab_off || !m_all || !s_all) return MCM_ERR_INVALID_ARG;
+    if (((uintptr_t)m_all & 7) != 0 || ((uintptr_t)s_all & 3) != 0) return MCM_ERR_INVALID_ARG;
+    std::vector<ChainInfo> ci((size_t)count);
+    int64_t p_len = 0;
+    for (int32_t b = 0; b < count; ++b) {
+        if (p_off[b] < 0 || tab_off[b] < 0 || n[b] < 1) return MCM_ERR_INVALID_ARG;
+        mcm_status st = check_chain(p_all + p_off[b], n[b], &ci[b]);
+        if (st != MCM_OK) return st;
+        if (p_off[b] + n[b] + 1 > p_len) p_len = p_off[b] + n[b] + 1;
+    }
+    if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
+
+    // All dims in one upload: p_len int32 (padded to 8 bytes), then p_len doubles.
+    const size_t np = (size_t)p_len;
+    const size_t off_d = (np * sizeof(int32_t) + 7) / 8 * 8;
+    void *dev = nullptr;
+    mcm_status st = upload_blob(stream, &dev, off_d + np * sizeof(double), [&](char *h) {
+        memcpy(h, p_all, np * sizeof(int32_t));
+        double *hd = (double *)(h + off_d);
+        for (size_t t = 0; t < np; ++t) hd[t] = (double)p_all[t];
+    });
+    if (st != MCM_OK) return st;
+    const int32_t *p_dev = (const int32_t *)dev;
+    const double *pd_dev = (const double *)((char *)dev + off_d);
+
+    TiledPlan plan;
+    std::vector<int> ids;
+    int maxNT = 0;
+    for (int32_t b = 0; b < count; ++b) {
+        if (!tiled_accepts(ci[b])) continue;
+        const int c = plan_add_chain(plan, ci[b], tab_off[b], tab_off[b], p_off[b]);
+        ids.push_back(c);
+        if (plan.NT[c] > maxNT) maxNT = plan.NT[c];
+    }
+    for (int D = 0; D < maxNT; ++D) plan_add_iteration(plan, ids, std::vector<int>(ids.size(), D));
+    st = run_tiled_plan(plan, p_dev, pd_dev, m_all, s_all, stream);
+    for (int32_t b = 0; b < count && st == MCM_OK; ++b) {
+        if (tiled_accepts(ci[b])) continue;
+        DeviceChain dc;
+        dc.p = p_dev + p_off[b];
+        dc.pd = pd_dev + p_off[b];
+        st = run_wavefront(dc, ci[b], m_all + tab_off[b], s_all + tab_off[b], stream);
+    }
+    ws_free(dev, stream);
     return st;
 }
 

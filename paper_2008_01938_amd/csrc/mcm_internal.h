@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+#include <vector>
+
 #include "../../include/mcm.h"
 
 namespace mcm {
@@ -41,13 +44,75 @@ struct DeviceChain {
 hipError_t ws_alloc(void **ptr, size_t bytes, hipStream_t stream);
 void ws_free(void *ptr, hipStream_t stream);
 
+// Allocate `bytes` of stream-ordered device memory and enqueue its upload:
+// `fill` writes the contents into pinned staging memory, which is copied to
+// the device on `stream`.  The caller frees *dev with ws_free.
+mcm_status upload_blob(hipStream_t stream, void **dev, size_t bytes,
+                       const std::function<void(char *)> &fill);
+
+// ------------------------------------------------------------------------
+// Tiled launches are driven by tables in device memory, so one launch can
+// serve many chains, each at its own tile-diagonal.
+// ------------------------------------------------------------------------
+struct TileChain {      // one chain of a tiled launch
+    int64_t m_off;      // element offset of its n*n int64 m table in m_all
+    int64_t s_off;      // element offset of its n*n int32 s table in s_all
+    int64_t p_off;      // offset of its p[0] in the int32 and fp64 dimension arrays
+    int32_t n;          // matrices
+    int32_t kb;         // fp64 key: bits below the cost (53 - cost bits, <= 20)
+    int32_t kbits;      // bits of a split index in packed partial minima
+    int32_t pad;
+};
+
+struct TileSeg {        // consecutive workgroups of one launch working on one chain
+    int64_t part_off;   // element offset of the chain's packed partial minima
+    int32_t first;      // first workgroup index of the segment
+    int32_t chain;      // index into the TileChain table
+    int32_t D;          // tile-diagonal
+    int32_t P;          // bulk chunks per tile (0: no bulk partials)
+    int32_t KS;         // splits per bulk chunk
+    int32_t pad;
+};
+
+enum TiledKernel { TK_TRI = 0, TK_BULK = 1, TK_CLOSE = 2 };
+
+struct TiledLaunch {    // one kernel launch of a tiled plan
+    int kind;           // TiledKernel
+    int seg_begin;      // first TileSeg of the launch in the plan's table
+    int nseg;
+    int blocks;         // workgroups
+    double evals;       // split evaluations the launch performs
+};
+
 // Wavefront path (int64, any valid input).
 mcm_status run_wavefront(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int32_t *s,
                          hipStream_t stream);
 
-// Tiled path (exact integers carried in fp64; see can_run_tiled).
+// Tiled path (exact integers carried in fp64; see tiled_accepts).
 bool tiled_accepts(const ChainInfo &ci);
 mcm_status run_tiled(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int32_t *s,
                      hipStream_t stream);
+
+// A sequence of tiled launches over several chains.
+struct TiledPlan {
+    std::vector<TileChain> chains;
+    std::vector<int32_t> NT;           // tiles per side of each chain
+    std::vector<TileSeg> segs;
+    std::vector<TiledLaunch> launches;
+    size_t part_elems = 0;             // partial-minima buffer (uint64) the plan needs
+};
+
+// Add a chain (m_off/s_off/p_off as in TileChain); returns its index.
+int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t s_off,
+                   int64_t p_off);
+// Append one iteration: each listed chain advances by one tile-diagonal
+// (D = 0 runs its diagonal tiles; D >= 1 its bulk and closure).  Chains
+// with D >= NT are skipped.  Launches: diagonal tiles, bulk, closure.
+void plan_add_iteration(TiledPlan &plan, const std::vector<int> &chain_ids,
+                        const std::vector<int> &Ds);
+// Execute a plan on `stream`: p (int32) and pd (fp64) hold every chain's
+// dimensions at its p_off; m_all / s_all its tables at m_off / s_off.
+mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double *pd,
+                          int64_t *m_all, int32_t *s_all, hipStream_t stream);
 
 }  // namespace mcm

@@ -117,3 +117,28 @@ def test_chain_create_rejects_bad_input(lib):
     assert lib.mcm_chain_solve(None, 0, ctypes.c_void_p(m.ctypes.data),
                                ctypes.c_void_p(s.ctypes.data), ctypes.c_void_p(0)) == \
         binding.ERR_INVALID_ARG
+
+
+def test_batched_rejects_bad_input_before_device(lib):
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    i64 = ctypes.POINTER(ctypes.c_int64)
+    m = np.full(64, 7, dtype=np.int64)
+    s = np.full(64, 7, dtype=np.int32)
+
+    def call(ns, p_off, p_all, tab, count=None):
+        ns = np.asarray(ns, dtype=np.int32)
+        p_off = np.asarray(p_off, dtype=np.int64)
+        p_all = np.asarray(p_all, dtype=np.int32)
+        tab = np.asarray(tab, dtype=np.int64)
+        return lib.mcm_solve_batched(ns.size if count is None else count, ns.ctypes.data_as(i32),
+                                     p_off.ctypes.data_as(i64), p_all.ctypes.data_as(i32),
+                                     tab.ctypes.data_as(i64), ctypes.c_void_p(m.ctypes.data),
+                                     ctypes.c_void_p(s.ctypes.data), ctypes.c_void_p(0))
+
+    assert call([2, 0], [0, 0], [3, 4, 5], [0, 4]) == binding.ERR_INVALID_ARG      # n = 0
+    assert call([2, 1], [0, 1], [3, 0, 5], [0, 4]) == binding.ERR_INVALID_ARG      # p = 0
+    assert call([2], [-1], [3, 4, 5], [0]) == binding.ERR_INVALID_ARG              # offset
+    assert call([2], [0], [1 << 21] * 3, [0]) == binding.ERR_OVERFLOW
+    assert call([2], [0], [3, 4, 5], [0], count=-1) == binding.ERR_INVALID_ARG
+    assert call([], [], [], [], count=0) == binding.OK                             # no-op
+    assert np.all(m == 7) and np.all(s == 7)

@@ -1,0 +1,102 @@
+"""Batched solves (mcm_solve_batched) vs the CPU oracle, bit-exact."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_01938_amd import binding, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    binding.load()
+
+
+def run_batch(batch: workloads.Batch):
+    import torch
+    ns = batch.ns
+    off = binding.table_offsets(ns)
+    total = int(off[-1] + int(ns[-1]) ** 2) if ns.size else 1
+    m_all = torch.full((max(total, 1),), -9, dtype=torch.int64, device="cuda")
+    s_all = torch.full((max(total, 1),), -9, dtype=torch.int32, device="cuda")
+    _say(f"[gpu] batched count={ns.size} max_n={int(ns.max()) if ns.size else 0}")
+    binding.solve_batched_into(ns, batch.p_off, batch.p_all, off, m_all, s_all)
+    torch.cuda.synchronize()
+    return off, m_all.cpu().numpy(), s_all.cpu().numpy()
+
+
+def check_against_oracle(batch, off, m_all, s_all, which=None):
+    thr = oracle.default_threads()
+    idx = range(batch.ns.size) if which is None else which
+    for b in idx:
+        n = int(batch.ns[b])
+        o = int(off[b])
+        om, os_ = oracle.fill(batch.dims(b), threads=thr)
+        gm = m_all[o:o + n * n].reshape(n, n)
+        gs = s_all[o:o + n * n].reshape(n, n)
+        assert np.array_equal(gm, om), f"chain {b} (n={n}): m differs"
+        assert np.array_equal(gs, os_), f"chain {b} (n={n}): s differs"
+
+
+def test_mixed_sizes_and_paths():
+    rng = np.random.default_rng(11)
+    chains = []
+    for t in range(40):
+        n = int(rng.integers(1, 330))
+        chains.append(workloads.uniform_dims(n, 1, 1024, 100 + t))
+    # Outside the fp64-exact range: takes the int64 wavefront inside the batch.
+    chains.append(workloads.uniform_dims(20, (1 << 19) - 9, 1 << 19, 5))
+    chains += [workloads.all_equal(130, 7), workloads.tie_heavy(200, 3), np.array([5, 6])]
+    batch = workloads.make_batch(chains)
+    off, m_all, s_all = run_batch(batch)
+    check_against_oracle(batch, off, m_all, s_all)
+
+
+def test_shared_dims_and_gapped_tables():
+    import torch
+    p = workloads.uniform_dims(300, 1, 1024, 9)
+    # Three chains read overlapping windows of one dims array.
+    ns = np.array([300, 150, 64], dtype=np.int32)
+    p_off = np.array([0, 100, 236], dtype=np.int64)
+    tab = np.array([0, 300 * 300 + 17, 300 * 300 + 17 + 150 * 150 + 5], dtype=np.int64)
+    total = int(tab[-1] + 64 * 64)
+    m_all = torch.full((total,), -9, dtype=torch.int64, device="cuda")
+    s_all = torch.full((total,), -9, dtype=torch.int32, device="cuda")
+    binding.solve_batched_into(ns, p_off, p, tab, m_all, s_all)
+    torch.cuda.synchronize()
+    m_h, s_h = m_all.cpu().numpy(), s_all.cpu().numpy()
+    for b in range(3):
+        n, o, po = int(ns[b]), int(tab[b]), int(p_off[b])
+        om, os_ = oracle.fill(p[po:po + n + 1])
+        assert np.array_equal(m_h[o:o + n * n].reshape(n, n), om)
+        assert np.array_equal(s_h[o:o + n * n].reshape(n, n), os_)
+    # Gaps between tables are untouched.
+    assert np.all(m_h[300 * 300:300 * 300 + 17] == -9)
+    assert np.all(s_h[300 * 300 + 17 + 150 * 150:tab[2]] == -9)
+
+
+def test_empty_batch_is_noop():
+    import torch
+    m = torch.zeros(4, dtype=torch.int64, device="cuda")
+    s = torch.zeros(4, dtype=torch.int32, device="cuda")
+    binding.solve_batched_into([], [], [1], [], m, s)
+    torch.cuda.synchronize()
+
+
+def test_batched_4096_config():
+    # The batched benchmark workload: 4096 chains, n in [16, 512], dims in
+    # [1, 256], seed 3 -- every chain checked against the oracle.
+    batch = workloads.batched_4096()
+    off, m_all, s_all = run_batch(batch)
+    check_against_oracle(batch, off, m_all, s_all)
