@@ -162,6 +162,66 @@ int32_t mcm_chain_n(const mcm_chain *chain);
 void mcm_chain_destroy(mcm_chain *chain, hipStream_t stream);
 
 /*
+ * Request server: continuous batching of many chains on one device.
+ *
+ * The server owns one device arena of `mem_budget` bytes from which each
+ * admitted request gets its dims and its m/s tables (n*n*12 bytes plus the
+ * dims), a FIFO queue, and a scheduler thread.  Every iteration the
+ * scheduler admits queued requests in arrival order while a slot (at most
+ * `max_slots` requests hold memory at once) and arena memory are free,
+ * then advances every admitted, unfinished request by one tile-diagonal:
+ * one launch of each tiled kernel serves them all, each at its own
+ * tile-diagonal, so requests that arrive while others run join the next
+ * iteration and their work overlaps on the device.  Up to two iterations
+ * are in flight; a request is complete when the iteration holding its last
+ * tile-diagonal has finished on the device.  Results are bit-identical to
+ * mcm_solve of the same chain.  Chains outside the tiled path's
+ * fp64-exact range run the int64 wavefront in one iteration.
+ *
+ *   mcm_server_create  budget in bytes (> 0), max_slots >= 1; work runs on
+ *                      `stream` (0 = null stream).  MCM_ERR_NO_MEMORY if
+ *                      the arena cannot be allocated.
+ *   mcm_server_submit  validates p (host, n+1 dims, copied before return)
+ *                      and queues the request under the caller's `tag`.
+ *                      MCM_ERR_INVALID_ARG / MCM_ERR_OVERFLOW for a bad
+ *                      chain, MCM_ERR_NO_MEMORY if the request alone
+ *                      exceeds the arena; never blocks.
+ *   mcm_server_poll    moves up to `cap` completed requests into `out`
+ *                      (oldest first) and sets *count.  m and s are device
+ *                      pointers into the arena, valid until released.
+ *   mcm_server_release returns a completed (polled) request's memory to the
+ *                      arena.  The caller must have finished every read of
+ *                      its tables (work on the server's stream, or
+ *                      synchronised).  MCM_ERR_INVALID_ARG for an unknown
+ *                      tag.
+ *   mcm_server_stats   counters; any pointer may be NULL.
+ *   mcm_server_destroy stops the scheduler, waits for the device, frees
+ *                      the arena; pending requests are dropped.
+ *   mcm_clock_now      the steady clock the timestamps use, in seconds.
+ * Times are seconds on mcm_clock_now's clock: t_submit when submitted,
+ * t_admit when memory was granted, t_done when completion was observed.
+ */
+typedef struct mcm_server mcm_server;
+typedef struct mcm_request_info {
+    uint64_t tag;
+    int32_t n;
+    int32_t status;      /* mcm_status of the request */
+    int64_t *m;          /* device, n*n int64 (arena memory) */
+    int32_t *s;          /* device, n*n int32 (arena memory) */
+    double t_submit, t_admit, t_done;
+} mcm_request_info;
+
+mcm_status mcm_server_create(size_t mem_budget, int32_t max_slots, hipStream_t stream,
+                             mcm_server **out);
+mcm_status mcm_server_submit(mcm_server *srv, const int32_t *p, int32_t n, uint64_t tag);
+mcm_status mcm_server_poll(mcm_server *srv, mcm_request_info *out, int32_t cap, int32_t *count);
+mcm_status mcm_server_release(mcm_server *srv, uint64_t tag);
+mcm_status mcm_server_stats(mcm_server *srv, int64_t *queued, int64_t *active,
+                            int64_t *completed, int64_t *iterations, int64_t *bytes_in_use);
+void mcm_server_destroy(mcm_server *srv);
+double mcm_clock_now(void);
+
+/*
  * Kernel-level profiling on the library's own launches (HIP events on the
  * stream each kernel is enqueued on).  Enabling clears the counters;
  * reading synchronises the recorded events.  Classes:

@@ -11,7 +11,7 @@ Importing the package loads nothing; the library is loaded on first use.
 from __future__ import annotations
 
 __all__ = ["solve", "solve_into", "check_chain", "select_algo", "MCMError", "Chain",
-           "solve_batched_into", "table_offsets",
+           "solve_batched_into", "table_offsets", "Server",
            "profile_enable", "profile_read", "ALGOS"]
 
 

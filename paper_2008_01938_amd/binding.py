@@ -33,8 +33,17 @@ PROF_SETUP, PROF_BULK, PROF_CLOSE, PROF_WAVE, PROF_BATCH = range(5)
 EXPORTED = (
     "mcm_status_string", "mcm_version", "mcm_check_chain", "mcm_select_algo",
     "mcm_solve", "mcm_solve_algo", "mcm_solve_batched", "mcm_chain_create", "mcm_chain_solve", "mcm_chain_n",
-    "mcm_chain_destroy", "mcm_profile_enable", "mcm_profile_read",
+    "mcm_chain_destroy", "mcm_server_create", "mcm_server_submit", "mcm_server_poll",
+    "mcm_server_release", "mcm_server_stats", "mcm_server_destroy", "mcm_clock_now",
+    "mcm_profile_enable", "mcm_profile_read",
 )
+
+
+class RequestInfo(ctypes.Structure):
+    """mcm_request_info."""
+    _fields_ = [("tag", ctypes.c_uint64), ("n", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("m", ctypes.c_void_p), ("s", ctypes.c_void_p), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
 
 
 class MCMError(RuntimeError):
@@ -88,6 +97,22 @@ def load() -> ctypes.CDLL:
             lib.mcm_chain_n.restype = ctypes.c_int32
             lib.mcm_chain_destroy.argtypes = [vp, vp]
             lib.mcm_chain_destroy.restype = None
+            lib.mcm_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, vp,
+                                              ctypes.POINTER(vp)]
+            lib.mcm_server_create.restype = ctypes.c_int
+            lib.mcm_server_submit.argtypes = [vp, i32p, ctypes.c_int32, ctypes.c_uint64]
+            lib.mcm_server_submit.restype = ctypes.c_int
+            lib.mcm_server_poll.argtypes = [vp, ctypes.POINTER(RequestInfo), ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_int32)]
+            lib.mcm_server_poll.restype = ctypes.c_int
+            lib.mcm_server_release.argtypes = [vp, ctypes.c_uint64]
+            lib.mcm_server_release.restype = ctypes.c_int
+            lib.mcm_server_stats.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int64)] * 5
+            lib.mcm_server_stats.restype = ctypes.c_int
+            lib.mcm_server_destroy.argtypes = [vp]
+            lib.mcm_server_destroy.restype = None
+            lib.mcm_clock_now.argtypes = []
+            lib.mcm_clock_now.restype = ctypes.c_double
             lib.mcm_profile_enable.argtypes = [ctypes.c_int32]
             lib.mcm_profile_enable.restype = None
             lib.mcm_profile_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -248,6 +273,91 @@ class Chain:
         if self._h:
             load().mcm_chain_destroy(self._h, ctypes.c_void_p(_stream_handle(stream)))
             self._h = None
+
+
+def clock_now() -> float:
+    """Seconds on the steady clock the server's timestamps use."""
+    return float(load().mcm_clock_now())
+
+
+_hip = None
+
+
+def copy_device_to_host(dst: np.ndarray, src_ptr: int) -> None:
+    """Synchronous hipMemcpy of dst.nbytes from device address src_ptr."""
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    rc = _hip.hipMemcpy(ctypes.c_void_p(dst.ctypes.data), ctypes.c_void_p(src_ptr),
+                        dst.nbytes, 2)  # hipMemcpyDeviceToHost
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")
+
+
+class Server:
+    """mcm_server: continuous batching of chain solves on one device."""
+
+    def __init__(self, mem_budget: int, max_slots: int = 256, stream=None):
+        h = ctypes.c_void_p()
+        st = load().mcm_server_create(int(mem_budget), int(max_slots),
+                                      ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(h))
+        if st != OK:
+            raise MCMError(st, "mcm_server_create")
+        self._h = h
+        self._buf = (RequestInfo * 256)()
+
+    def submit(self, p, tag: int) -> None:
+        a = _dims(p)
+        st = load().mcm_server_submit(self._h, _p_ptr(a), a.size - 1, ctypes.c_uint64(tag))
+        if st != OK:
+            raise MCMError(st, "mcm_server_submit")
+
+    def poll(self) -> list:
+        """Completed requests (RequestInfo copies), oldest first."""
+        out = []
+        cnt = ctypes.c_int32(0)
+        while True:
+            st = load().mcm_server_poll(self._h, self._buf, len(self._buf), ctypes.byref(cnt))
+            if st != OK:
+                raise MCMError(st, "mcm_server_poll")
+            out.extend(RequestInfo.from_buffer_copy(self._buf[i]) for i in range(cnt.value))
+            if cnt.value < len(self._buf):
+                return out
+
+    def fetch(self, info: RequestInfo):
+        """Copy a completed request's tables to host numpy arrays."""
+        n = info.n
+        m = np.empty((n, n), dtype=np.int64)
+        s = np.empty((n, n), dtype=np.int32)
+        copy_device_to_host(m, info.m)
+        copy_device_to_host(s, info.s)
+        return m, s
+
+    def release(self, tag: int) -> None:
+        st = load().mcm_server_release(self._h, ctypes.c_uint64(tag))
+        if st != OK:
+            raise MCMError(st, "mcm_server_release")
+
+    def stats(self) -> dict:
+        v = [ctypes.c_int64(0) for _ in range(5)]
+        st = load().mcm_server_stats(self._h, *[ctypes.byref(x) for x in v])
+        if st != OK:
+            raise MCMError(st, "mcm_server_stats")
+        return dict(zip(["queued", "active", "completed", "iterations", "bytes_in_use"],
+                        [x.value for x in v]))
+
+    def close(self) -> None:
+        if self._h:
+            load().mcm_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def profile_enable(on: bool = True) -> None:

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(NTH) void k_bulk(const TileChain *__restrict__ chai
     const TileChain ch = chains[sg.chain];
     const int32_t n = ch.n, D = sg.D, KS = sg.KS, P = sg.P, kb = ch.kb, kbits = ch.kbits;
     const int64_t *__restrict__ m = m_all + ch.m_off;
-    const double *__restrict__ pd = pd_all + ch.p_off;
+    const double *__restrict__ pd = pd_all + ch.pd_off;
     const int local = blockIdx.x - sg.first;
     const int tile = local / P;
     const int chunk = local - tile * P;
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
     const int32_t n = ch.n, D = sg.D, P = sg.P, kb = ch.kb, kbits = ch.kbits;
     int64_t *__restrict__ m = m_all + ch.m_off;
     int32_t *__restrict__ s = s_all + ch.s_off;
-    const double *__restrict__ pd = pd_all + ch.p_off;
+    const double *__restrict__ pd = pd_all + ch.pd_off;
     const uint64_t *__restrict__ part = part_all + sg.part_off;
     const int I = blockIdx.x - sg.first, J = I + D;
     const int row0 = I * T, col0 = J * T;
@@ -537,12 +537,13 @@ bool tiled_accepts(const ChainInfo &ci)
 }
 
 int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t s_off,
-                   int64_t p_off)
+                   int64_t p_off, int64_t pd_off)
 {
     TileChain c{};
     c.m_off = m_off;
     c.s_off = s_off;
     c.p_off = p_off;
+    c.pd_off = pd_off;
     c.n = ci.n;
     c.kb = 53 - ci.cost_bits;
     if (c.kb > 20) c.kb = 20;
@@ -689,7 +690,7 @@ mcm_status run_tiled(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int
 {
     if (!tiled_accepts(ci)) return MCM_ERR_UNSUPPORTED;
     TiledPlan plan;
-    const int c = plan_add_chain(plan, ci, 0, 0, 0);
+    const int c = plan_add_chain(plan, ci, 0, 0, 0, 0);
     for (int D = 0; D < plan.NT[c]; ++D) plan_add_iteration(plan, {c}, {D});
     return run_tiled_plan(plan, dc.p, dc.pd, m, s, stream);
 }

@@ -13,7 +13,6 @@
 #include "mcm_internal.h"
 
 namespace mcm {
-namespace {
 
 // ------------------------------------------------------------------------
 // Validation.
@@ -39,6 +38,8 @@ mcm_status check_chain(const int32_t *p, int32_t n, ChainInfo *ci)
     }
     return MCM_OK;
 }
+
+namespace {
 
 // ------------------------------------------------------------------------
 // Pinned staging for the host chain: a grow-only pool of pinned buffers,
@@ -176,6 +177,20 @@ mcm_status upload_chain(const int32_t *p, int32_t n, hipStream_t stream, void **
 }
 
 }  // namespace
+
+mcm_status upload_to(hipStream_t stream, void *dst, size_t bytes,
+                     const std::function<void(char *)> &fill)
+{
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return MCM_ERR_DEVICE;
+    StagingBuf *sb = stage_acquire(bytes, device);
+    if (!sb) return MCM_ERR_NO_MEMORY;
+    fill((char *)sb->host);
+    hipError_t e = hipMemcpyAsync(dst, sb->host, bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(sb->done, stream);
+    stage_release(sb);
+    return e == hipSuccess ? MCM_OK : MCM_ERR_DEVICE;
+}
 
 mcm_status upload_blob(hipStream_t stream, void **dev_out, size_t bytes,
                        const std::function<void(char *)> &fill)
@@ -357,7 +372,7 @@ mcm_status mcm_solve_batched(int32_t count, const int32_t *n, const int64_t *p_o
     int maxNT = 0;
     for (int32_t b = 0; b < count; ++b) {
         if (!tiled_accepts(ci[b])) continue;
-        const int c = plan_add_chain(plan, ci[b], tab_off[b], tab_off[b], p_off[b]);
+        const int c = plan_add_chain(plan, ci[b], tab_off[b], tab_off[b], p_off[b], p_off[b]);
         ids.push_back(c);
         if (plan.NT[c] > maxNT) maxNT = plan.NT[c];
     }

@@ -40,6 +40,14 @@ struct DeviceChain {
     const double *pd = nullptr;   // n+1 doubles (exact copies of p)
 };
 
+// Host validation of a chain (no device call); fills ci on success.
+mcm_status check_chain(const int32_t *p, int32_t n, ChainInfo *ci);
+
+// Enqueue a copy of `bytes` host bytes, written by `fill` into pinned
+// staging memory, to the existing device buffer `dst` on `stream`.
+mcm_status upload_to(hipStream_t stream, void *dst, size_t bytes,
+                     const std::function<void(char *)> &fill);
+
 // Stream-ordered workspace allocation (hipMallocAsync on the call's stream).
 hipError_t ws_alloc(void **ptr, size_t bytes, hipStream_t stream);
 void ws_free(void *ptr, hipStream_t stream);
@@ -57,7 +65,8 @@ mcm_status upload_blob(hipStream_t stream, void **dev, size_t bytes,
 struct TileChain {      // one chain of a tiled launch
     int64_t m_off;      // element offset of its n*n int64 m table in m_all
     int64_t s_off;      // element offset of its n*n int32 s table in s_all
-    int64_t p_off;      // offset of its p[0] in the int32 and fp64 dimension arrays
+    int64_t p_off;      // element offset of its p[0] in the int32 dimension array
+    int64_t pd_off;     // element offset of its p[0] in the fp64 dimension array
     int32_t n;          // matrices
     int32_t kb;         // fp64 key: bits below the cost (53 - cost bits, <= 20)
     int32_t kbits;      // bits of a split index in packed partial minima
@@ -102,16 +111,17 @@ struct TiledPlan {
     size_t part_elems = 0;             // partial-minima buffer (uint64) the plan needs
 };
 
-// Add a chain (m_off/s_off/p_off as in TileChain); returns its index.
+// Add a chain (offsets as in TileChain); returns its index.
 int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t s_off,
-                   int64_t p_off);
+                   int64_t p_off, int64_t pd_off);
 // Append one iteration: each listed chain advances by one tile-diagonal
 // (D = 0 runs its diagonal tiles; D >= 1 its bulk and closure).  Chains
 // with D >= NT are skipped.  Launches: diagonal tiles, bulk, closure.
 void plan_add_iteration(TiledPlan &plan, const std::vector<int> &chain_ids,
                         const std::vector<int> &Ds);
 // Execute a plan on `stream`: p (int32) and pd (fp64) hold every chain's
-// dimensions at its p_off; m_all / s_all its tables at m_off / s_off.
+// dimensions at its p_off / pd_off; m_all / s_all its tables at m_off /
+// s_off.
 mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double *pd,
                           int64_t *m_all, int32_t *s_all, hipStream_t stream);
 

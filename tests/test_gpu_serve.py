@@ -1,0 +1,93 @@
+"""The continuous-batching server: every served result equals the same
+chain solved alone (and the oracle), under overlap, admission limits and
+mixed kernel paths."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_01938_amd import binding, serve, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    binding.load()
+
+
+def small_stream(count, rate, seed, n_hi=700):
+    return workloads.serving_stream(count=count, rate=rate, seed=seed, n_lo=8, n_hi=n_hi)
+
+
+def test_served_equals_alone_and_oracle():
+    st = small_stream(80, rate=4000.0, seed=21)
+    _say(f"[gpu] serve 80 requests, max n={int(st.batch.ns.max())}")
+    res = serve.run_served(st, mem_budget=2 << 30, max_slots=64, keep=range(80))
+    assert res.count == 80
+    import torch
+    for i in range(80):
+        p = st.batch.dims(i)
+        m_alone, s_alone = binding.solve(p)
+        torch.cuda.synchronize()
+        om, os_ = oracle.fill(p, threads=oracle.default_threads())
+        m, s = res.outputs[i]
+        assert np.array_equal(m, om) and np.array_equal(s, os_), f"request {i}"
+        assert np.array_equal(m, m_alone.cpu().numpy()) and np.array_equal(s, s_alone.cpu().numpy())
+
+
+def test_tiny_budget_forces_queueing():
+    st = small_stream(30, rate=1e6, seed=5, n_hi=400)     # all arrive at once
+    nmax = int(st.batch.ns.max())
+    budget = nmax * nmax * 12 + 64 * 1024                 # about one request at a time
+    _say(f"[gpu] serve with budget {budget} bytes")
+    res = serve.run_served(st, mem_budget=budget, max_slots=64, keep=range(30))
+    for i in range(30):
+        om, os_ = oracle.fill(st.batch.dims(i))
+        assert np.array_equal(res.outputs[i][0], om) and np.array_equal(res.outputs[i][1], os_)
+
+
+def test_one_slot_serialises():
+    st = small_stream(12, rate=1e6, seed=6, n_hi=300)
+    res = serve.run_served(st, mem_budget=1 << 30, max_slots=1, keep=range(12))
+    for i in range(12):
+        om, os_ = oracle.fill(st.batch.dims(i))
+        assert np.array_equal(res.outputs[i][0], om) and np.array_equal(res.outputs[i][1], os_)
+
+
+def test_mixed_paths_and_errors():
+    with binding.Server(1 << 30, 16) as srv:
+        big = workloads.uniform_dims(30, (1 << 19) - 9, 1 << 19, 4)   # int64 wavefront
+        small = workloads.uniform_dims(150, 1, 1024, 8)
+        srv.submit(big, 1)
+        srv.submit(small, 2)
+        with pytest.raises(binding.MCMError) as e:
+            srv.submit(np.array([3, 0, 4], dtype=np.int32), 3)
+        assert e.value.status == binding.ERR_INVALID_ARG
+        with pytest.raises(binding.MCMError) as e:
+            srv.submit(workloads.uniform_dims(12000, 1, 4, 1), 4)      # > budget
+        assert e.value.status == binding.ERR_NO_MEMORY
+        got = {}
+        t_end = binding.clock_now() + 60
+        while len(got) < 2 and binding.clock_now() < t_end:
+            for info in srv.poll():
+                assert info.status == binding.OK
+                got[int(info.tag)] = srv.fetch(info)
+                srv.release(int(info.tag))
+        assert set(got) == {1, 2}
+        for tag, p in ((1, big), (2, small)):
+            om, os_ = oracle.fill(p)
+            assert np.array_equal(got[tag][0], om) and np.array_equal(got[tag][1], os_)
+        with pytest.raises(binding.MCMError):
+            srv.release(99)
+        stats = srv.stats()
+        assert stats["completed"] == 2 and stats["active"] == 0 and stats["bytes_in_use"] == 0
