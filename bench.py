@@ -27,6 +27,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -102,6 +104,59 @@ def cpu_baseline(p, target_s: float):
                       f"cells of each diagonal)"}
 
 
+def bench_batched(binding, workloads, torch, reps: int = 3):
+    """4096 chains (n in [16, 512], dims in [1, 256], seed 3): one
+    mcm_solve_batched call against 4096 plain per-chain solves on one stream
+    (chains already resident on the device in both cases)."""
+    b = workloads.batched_4096()
+    off = binding.table_offsets(b.ns)
+    total = int(off[-1] + int(b.ns[-1]) ** 2)
+    m_all = torch.empty(total, dtype=torch.int64, device="cuda")
+    s_all = torch.empty(total, dtype=torch.int32, device="cuda")
+    binding.solve_batched_into(b.ns, b.p_off, b.p_all, off, m_all, s_all)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        binding.solve_batched_into(b.ns, b.p_off, b.p_all, off, m_all, s_all)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    chains = [binding.Chain(b.dims(i)) for i in range(b.ns.size)]
+    views = [(m_all[int(off[i]):int(off[i]) + int(n) ** 2],
+              s_all[int(off[i]):int(off[i]) + int(n) ** 2]) for i, n in enumerate(b.ns)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ch, (mv, sv) in zip(chains, views):
+        ch.solve_into(mv, sv)
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t0
+    for ch in chains:
+        ch.close()
+    evals = float(np.sum((b.ns.astype(np.float64) ** 3 - b.ns) / 6))
+    count = int(b.ns.size)
+    return {"workload": "mcm_batched_4096 (n in [16,512], dims [1,256], seed 3)",
+            "instances_per_s": count / best, "ms": 1e3 * best,
+            "split_evals_per_s": evals / best,
+            "plain_instances_per_s": count / plain, "plain_ms": 1e3 * plain,
+            "speedup_vs_plain": plain / best,
+            "note": "batched time includes the host dims upload of mcm_solve_batched"}
+
+
+def bench_serving(binding, workloads, torch, count: int, rate: float):
+    """Open-loop Poisson stream (seed 4, n log-uniform in [8, 4096], dims in
+    [1, 1024]): continuous-batching server against plain FIFO solves."""
+    from paper_2008_01938_amd import serve
+    st = workloads.serving_stream(count=count, rate=rate, seed=4)
+    served = serve.run_served(st, mem_budget=24 << 30, max_slots=256).summary()
+    plain = serve.run_plain(st).summary()
+    return {"workload": f"mcm_serving (first {count} requests of the seed-4 stream, "
+                        f"Poisson {rate:g}/s, n log-uniform [8,4096], dims [1,1024])",
+            "served": served, "plain": plain,
+            "p99_speedup_vs_plain": plain["p99_ms"] / served["p99_ms"],
+            "p50_speedup_vs_plain": plain["p50_ms"] / served["p50_ms"]}
+
+
 def traffic_probe(binding, torch, chain, m, s):
     """One solve, then a plain device copy of a known size, for counter
     collection under rocprofv3 --pmc (FETCH_SIZE / WRITE_SIZE)."""
@@ -128,6 +183,10 @@ def main() -> int:
                     help="wall time target of the CPU-baseline sample (0 = skip)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one solve plus a 1 GiB copy, for rocprofv3 --pmc runs")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched section")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-rate", type=float, default=600.0, help="Poisson arrivals per second")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -136,7 +195,6 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
-    import numpy as np  # noqa: F401
     import torch
 
     from paper_2008_01938_amd import binding, workloads
@@ -220,10 +278,18 @@ def main() -> int:
         "roofline": roofline,
         "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in prof.items()},
     }
+    chain.close()
+    del m, s
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = bench_batched(binding, workloads, torch)
+    if not args.no_serving:
+        out["serving"] = bench_serving(binding, workloads, torch, args.serve_requests,
+                                       args.serve_rate)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(out), flush=True)
-    chain.close()
     return 0
 
 

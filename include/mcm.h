@@ -216,6 +216,9 @@ mcm_status mcm_server_create(size_t mem_budget, int32_t max_slots, hipStream_t s
 mcm_status mcm_server_submit(mcm_server *srv, const int32_t *p, int32_t n, uint64_t tag);
 mcm_status mcm_server_poll(mcm_server *srv, mcm_request_info *out, int32_t cap, int32_t *count);
 mcm_status mcm_server_release(mcm_server *srv, uint64_t tag);
+/* Arena bytes a request for chain p (host, n+1 dims) holds while admitted:
+ * its dims, m and s tables, and its partial minima.  0 if p is invalid. */
+size_t mcm_server_request_bytes(const int32_t *p, int32_t n);
 mcm_status mcm_server_stats(mcm_server *srv, int64_t *queued, int64_t *active,
                             int64_t *completed, int64_t *iterations, int64_t *bytes_in_use);
 void mcm_server_destroy(mcm_server *srv);

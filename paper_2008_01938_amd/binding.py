@@ -34,7 +34,7 @@ EXPORTED = (
     "mcm_status_string", "mcm_version", "mcm_check_chain", "mcm_select_algo",
     "mcm_solve", "mcm_solve_algo", "mcm_solve_batched", "mcm_chain_create", "mcm_chain_solve", "mcm_chain_n",
     "mcm_chain_destroy", "mcm_server_create", "mcm_server_submit", "mcm_server_poll",
-    "mcm_server_release", "mcm_server_stats", "mcm_server_destroy", "mcm_clock_now",
+    "mcm_server_release", "mcm_server_request_bytes", "mcm_server_stats", "mcm_server_destroy", "mcm_clock_now",
     "mcm_profile_enable", "mcm_profile_read",
 )
 
@@ -107,6 +107,8 @@ def load() -> ctypes.CDLL:
             lib.mcm_server_poll.restype = ctypes.c_int
             lib.mcm_server_release.argtypes = [vp, ctypes.c_uint64]
             lib.mcm_server_release.restype = ctypes.c_int
+            lib.mcm_server_request_bytes.argtypes = [i32p, ctypes.c_int32]
+            lib.mcm_server_request_bytes.restype = ctypes.c_size_t
             lib.mcm_server_stats.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int64)] * 5
             lib.mcm_server_stats.restype = ctypes.c_int
             lib.mcm_server_destroy.argtypes = [vp]
@@ -273,6 +275,12 @@ class Chain:
         if self._h:
             load().mcm_chain_destroy(self._h, ctypes.c_void_p(_stream_handle(stream)))
             self._h = None
+
+
+def server_request_bytes(p) -> int:
+    """Arena bytes the server holds for a request of chain p (0 if invalid)."""
+    a = _dims(p)
+    return int(load().mcm_server_request_bytes(_p_ptr(a), a.size - 1))
 
 
 def clock_now() -> float:

@@ -14,17 +14,23 @@
 //   (b) k in [JT, j-1]         left operand in the tile itself (to the
 //                              left), right operand in diagonal tile (J,J).
 //
+// The bulk range splits once more.  Its two end blocks, k in
+// [(I+1)T-1, (I+2)T-2] and [(J-1)T, JT-1], read tiles of tile-diagonal
+// D-1; the interior between them reads only tiles of diagonals <= D-2.
+//
 // k_tri fills the diagonal tiles (all their splits stay inside the tile).
-// k_bulk evaluates the bulk range of every tile of one tile-diagonal: a
-// min-plus-like reduction where the A panel (rows of I, columns k) and the
-// B panel (rows k+1, columns of J) are staged through LDS and each thread
-// keeps a 4 x 4 register microtile of running minima.  The bulk range is
-// cut into chunks spread over workgroups; each writes packed (cost, k)
-// partial minima.  k_close merges the partials and then adds the (a) and
-// (b) splits, which depend on cells of the same tile: cell (r, c) (local
-// row/column) needs the cells below it in its column and left of it in its
-// row, so the tile is swept in local anti-diagonals w = (T-1-r) + c, one
-// workgroup barrier per anti-diagonal, entirely in LDS.
+// k_bulk: a min-plus-like reduction over a chunk of a tile's bulk range.
+//         The A panel (rows of I, columns k) and the B panel (rows k+1,
+//         columns of J) are staged through LDS; each thread keeps a 4 x 4
+//         register microtile of running minima; each workgroup writes packed
+//         (cost, k) partial minima.
+// k_close: merges a tile's partials, then adds the (a) and (b) splits.
+//         Cell (r, c) (local row/column) needs the cells below it in its
+//         column and left of it in its row, so the tile is swept in local
+//         anti-diagonals w = (T-1-r) + c, one barrier per step, in LDS.
+// The closure of tile-diagonal D is long and latency-bound, and the interior
+// bulk of D+1 does not depend on it, so the two run concurrently on two
+// streams; the end blocks of D+1 follow the closure of D.
 //
 // Exact integers in fp64.  A candidate cost of cell (i, j) is at most
 // (j-i) * pmax^3 < 2^cost_bits.  The kernels carry
@@ -41,9 +47,9 @@
 namespace mcm {
 namespace {
 
-constexpr int T = 64;        // tile edge
-constexpr int KC = 16;       // k values staged per LDS round in k_bulk
-constexpr int NTH = 256;     // threads per workgroup
+constexpr int T = 64;          // tile edge
+constexpr int KC = 16;         // k values staged per LDS round (bulk)
+constexpr int NTH = 256;       // k_tri and k_bulk threads
 constexpr double kPad = 4611686018427387904.0;  // 2^62: never wins a min
 
 // The segment of a launch that workgroup b belongs to (segments are sorted
@@ -130,9 +136,37 @@ __global__ __launch_bounds__(NTH) void k_tri(const TileChain *__restrict__ chain
 }
 
 // ------------------------------------------------------------------------
-// Bulk splits of tile-diagonal D >= 2.  Workgroup b handles tile I = b / P
-// (J = I + D) and chunk b % P of its bulk range.  Thread (tx, ty) owns the
-// cells rows ty + 16a, columns tx + 16b (a, b = 0..3) of the tile.
+// Shared memory and launch shapes.
+// ------------------------------------------------------------------------
+constexpr int CG = 16;               // closure: lanes per row group
+constexpr int CTH = T * CG;          // closure: threads (16 waves, 4 per SIMD)
+constexpr int CS = T / CG;           // closure: register slots per lane
+constexpr int CROWS = 64 / CG;       // closure: rows per wave
+constexpr int CSTR = T + 8;          // closure: column stride (doubles) of its LDS tables
+
+struct BulkLds {
+    double As[2][KC][T + 1];  // As[kk][r] = m[row0+r][k] * 2^kb
+    double Bs[2][KC][T];      // Bs[kk][c] = m[k+1][col0+c] * 2^kb + (k - k0)
+    double Ps[2][KC];         // p[k+1]
+};
+
+struct CloseLds {
+    // Column-major with a column stride of CSTR doubles.  LDS has 32 banks
+    // of 4 bytes, so a 64-bit read is conflict-free when the 16 lanes served
+    // together touch distinct 8-byte words modulo 16; in a step those are
+    // the CG = 16 lanes of one row group, reading consecutive rows of one
+    // column.  Row T is a spare so slot addresses never need clamping.
+    double DJt[T][CSTR];  // DJt[c][q] = DJ[q][c] * 2^kb + T + q - 1 (1 <= q <= c), else 0
+    double Xt[T][CSTR];   // Xt[c][q]: bulk key, then final cost * 2^kb of cell (q, c)
+    int32_t Ks[T][T + 1];  // bulk split, then final split
+    double pJs[T + 1];     // p[col0 + q]
+};
+
+
+// ------------------------------------------------------------------------
+// Bulk: workgroup b of a segment takes tile b / nch and chunk b % nch of
+// the segment's split range; thread (tx, ty) owns the cells rows ty + 16a,
+// columns tx + 16b (a, b = 0..3) of the tile.
 // ------------------------------------------------------------------------
 __global__ __launch_bounds__(NTH) void k_bulk(const TileChain *__restrict__ chains,
                                               const TileSeg *__restrict__ segs, int nseg,
@@ -140,23 +174,22 @@ __global__ __launch_bounds__(NTH) void k_bulk(const TileChain *__restrict__ chai
                                               const double *__restrict__ pd_all,
                                               uint64_t *__restrict__ part_all)
 {
-    __shared__ double As[2][KC][T + 1];  // As[kk][r] = m[row0+r][k] * 2^kb
-    __shared__ double Bs[2][KC][T];      // Bs[kk][c] = m[k+1][col0+c] * 2^kb + (k - k0)
-    __shared__ double Ps[2][KC];         // p[k+1]
-
-    const int tid = threadIdx.x;
+    __shared__ BulkLds L;
     const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
     const TileChain ch = chains[sg.chain];
-    const int32_t n = ch.n, D = sg.D, KS = sg.KS, P = sg.P, kb = ch.kb, kbits = ch.kbits;
+    const int local = blockIdx.x - sg.first;
+    const int32_t n = ch.n, D = sg.D, KS = sg.KS, kb = ch.kb, kbits = ch.kbits;
     const int64_t *__restrict__ m = m_all + ch.m_off;
     const double *__restrict__ pd = pd_all + ch.pd_off;
-    const int local = blockIdx.x - sg.first;
-    const int tile = local / P;
-    const int chunk = local - tile * P;
+    const int tid = threadIdx.x;
+    const int tile = local / sg.nch;
+    const int chunk = local - tile * sg.nch;
     const int I = tile, J = tile + D;
     const int row0 = I * T, col0 = J * T;
-    const int k0 = (I + 1) * T - 1 + chunk * KS;
-    const int kend = min(k0 + KS, col0);  // exclusive end of this chunk
+    const int kbase = (I + 1) * T - 1 + sg.koff;
+    const int k0 = kbase + chunk * KS;
+    const int kend = min(k0 + KS, kbase + sg.klen);  // exclusive
+    const int rounds = (kend - k0 + KC - 1) / KC;
     const int nJ = min(T, n - col0);
     const double scale = ldexp(1.0, kb);
     const double inv_scale = ldexp(1.0, -kb);
@@ -180,44 +213,45 @@ __global__ __launch_bounds__(NTH) void k_bulk(const TileChain *__restrict__ chai
     double rp = 0.0;
     auto load = [&](int kc) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + NTH * u;
+        for (int v = 0; v < 4; ++v) {
+            const int e = tid + NTH * v;
             const int r = e / KC, kk = e % KC;
             const int k = kc + kk;
-            ra[u] = k < kend ? m[(size_t)(row0 + r) * n + k] : 0;
+            ra[v] = k < kend ? m[(size_t)(row0 + r) * n + k] : 0;
             const int kk2 = e / T, c = e % T;
             const int k2 = kc + kk2;
-            rb[u] = (k2 < kend && c < nJ) ? m[(size_t)(k2 + 1) * n + col0 + c] : 0;
+            rb[v] = (k2 < kend && c < nJ) ? m[(size_t)(k2 + 1) * n + col0 + c] : 0;
         }
         if (tid < KC) rp = (kc + tid < kend) ? pd[kc + tid + 1] : 0.0;
     };
     auto store = [&](int kc, int buf) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + NTH * u;
+        for (int v = 0; v < 4; ++v) {
+            const int e = tid + NTH * v;
             const int r = e / KC, kk = e % KC;
-            As[buf][kk][r] = (kc + kk < kend) ? (double)ra[u] * scale : kPad;
+            L.As[buf][kk][r] = (kc + kk < kend) ? (double)ra[v] * scale : kPad;
             const int kk2 = e / T, c = e % T;
-            Bs[buf][kk2][c] = fma((double)rb[u], scale, (double)(kc + kk2 - k0));
+            L.Bs[buf][kk2][c] = fma((double)rb[v], scale, (double)(kc + kk2 - k0));
         }
-        if (tid < KC) Ps[buf][tid] = rp;
+        if (tid < KC) L.Ps[buf][tid] = rp;
     };
 
     load(k0);
     store(k0, 0);
     __syncthreads();
     int buf = 0;
-    for (int kc = k0; kc < kend; kc += KC) {
-        const bool more = kc + KC < kend;
+    for (int rd = 0; rd < rounds; ++rd) {
+        const int kc = k0 + rd * KC;
+        const bool more = rd + 1 < rounds;
         if (more) load(kc + KC);
 #pragma unroll 4
         for (int kk = 0; kk < KC; ++kk) {
             double av[4], bv[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = As[buf][kk][ty + 16 * a];
+            for (int a = 0; a < 4; ++a) av[a] = L.As[buf][kk][ty + 16 * a];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) bv[b] = Bs[buf][kk][tx + 16 * b];
-            const double pk = Ps[buf][kk];
+            for (int b = 0; b < 4; ++b) bv[b] = L.Bs[buf][kk][tx + 16 * b];
+            const double pk = L.Ps[buf][kk];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -229,7 +263,7 @@ __global__ __launch_bounds__(NTH) void k_bulk(const TileChain *__restrict__ chai
         buf ^= 1;
     }
 
-    uint64_t *out = part_all + sg.part_off + (size_t)local * T * T;
+    uint64_t *out = part_all + sg.part_off + ((size_t)tile * sg.PT + sg.slot0 + chunk) * T * T;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
@@ -248,7 +282,7 @@ __global__ __launch_bounds__(NTH) void k_bulk(const TileChain *__restrict__ chai
 }
 
 // ------------------------------------------------------------------------
-// Closure of tile-diagonal D >= 1: one workgroup per tile (I, I+D).
+// Closure role: one workgroup per tile (I, I+D), D >= 1.
 //
 // Row group r (CG lanes) owns local row r.  At local anti-diagonal step w
 // it finalises cell (r, c), c = w - (T-1-r), from the bulk result and the
@@ -259,20 +293,12 @@ __global__ __launch_bounds__(NTH) void k_bulk(const TileChain *__restrict__ chai
 // lane g keeps the entries with q = g (mod CG) and c' = g (mod CG) in
 // registers (slot t holds index t*CG + g); only X[q+1][c] (other rows) and
 // DJ[c'+1][c] come from LDS.  Slots that do not apply hold 2^62 in their
-// register operand, so their terms never win and need no select.  Wave h
-// covers rows 8h..8h+7, whose (a) splits all lie in slots >= h: the step
-// body is instantiated per wave index so that range is static.  Two waves
-// per SIMD hide the fp64 issue latency a single wave would expose.  All
-// LDS reads of a step are issued before the first use; the row group's
-// minimum is formed with DPP lane permutations; one barrier per step
-// publishes the new cells to the other rows.
+// register operand, so their terms never win and need no select.  The
+// rows of wave h use (a) slots >= (h*CROWS)/CG only, so the step body is
+// instantiated per first slot.  All LDS reads of a step are issued before
+// the first use; the row group's minimum is formed with DPP lane
+// permutations; one barrier per step publishes the new cells.
 // ------------------------------------------------------------------------
-constexpr int CG = 8;               // lanes per row group
-constexpr int CTH = T * CG;          // 512 threads = 8 waves, 2 per SIMD
-constexpr int CS = T / CG;           // register slots per lane
-constexpr int CROWS = 64 / CG;       // rows per wave
-constexpr int CSTR = T + 8;          // column stride (doubles) of the closure's LDS tables
-
 template <int CTRL>
 __device__ __forceinline__ double dpp_perm(double v)
 {
@@ -283,12 +309,13 @@ __device__ __forceinline__ double dpp_perm(double v)
     return __builtin_bit_cast(double, o);
 }
 
-// Minimum over each aligned group of CG = 8 lanes (all lanes active).
+// Minimum over each aligned group of 16 lanes (all lanes active).
 __device__ __forceinline__ double min_group(double v)
 {
     v = fmin(v, dpp_perm<0xB1>(v));   // quad_perm [1,0,3,2]: lane ^ 1
     v = fmin(v, dpp_perm<0x4E>(v));   // quad_perm [2,3,0,1]: lane ^ 2
-    v = fmin(v, dpp_perm<0x141>(v));  // row_half_mirror: lane i <-> 7-i
+    v = fmin(v, dpp_perm<0x141>(v));  // row_half_mirror: i <-> 7-i
+    v = fmin(v, dpp_perm<0x140>(v));  // row_mirror: i <-> 15-i
     return v;
 }
 
@@ -296,14 +323,11 @@ struct CloseRegs {
     double DIr[CS], PIr[CS], PJr[CS], Xrow[CS];
 };
 
-// One anti-diagonal step for wave H (rows 16H..16H+15).  Returns the
-// minimum over the closure splits of this lane's cell (before the bulk).
-template <int H>
+template <int T0>  // first (a) slot any row of this wave uses
 __device__ __forceinline__ double close_step(const CloseRegs &R, const double (*Xt)[CSTR],
                                              const double (*DJt)[CSTR], int cc, int g,
                                              double pJc)
 {
-    constexpr int T0 = H * (CROWS / CG);  // first (a) slot any row of this wave uses
     double xa[CS], xb[CS];
 #pragma unroll
     for (int t = T0; t < CS; ++t) xa[t] = Xt[cc][t * CG + g + 1];
@@ -311,8 +335,7 @@ __device__ __forceinline__ double close_step(const CloseRegs &R, const double (*
     // whose cell is not final yet still holds Xrow = 2^62.
 #pragma unroll
     for (int t = 0; t < CS; ++t) xb[t] = DJt[cc][t * CG + g + 1];
-    // Independent terms, then a balanced min tree: a single running
-    // minimum would make every slot wait for the previous one.
+    // Independent terms, then a balanced min tree.
     double v[CS];
 #pragma unroll
     for (int t = 0; t < CS; ++t) {
@@ -333,27 +356,17 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
                                                const double *__restrict__ pd_all,
                                                const uint64_t *__restrict__ part_all)
 {
-    // Column-major with a column stride of CSTR = 72 doubles.  LDS has 32
-    // banks of 4 bytes, so a 64-bit read is conflict-free when the 16 lanes
-    // served together touch distinct 8-byte words modulo 16.  In a step,
-    // lane (i, g) of a wave (row 8h+i) reads row t*CG+g+1 of column c_lo+i:
-    // word (c_lo+i)*72 + 8t+g+1 = 8i + g + const (mod 16), distinct for the
-    // 16 lanes i = 0..1, g = 0..7 of each group.  Row T is a spare so slot
-    // addresses never need clamping.
-    __shared__ double DJt[T][CSTR];  // DJt[c][q] = DJ[q][c] * 2^kb + T + q - 1 (1 <= q <= c), else 0
-    __shared__ double Xt[T][CSTR];   // Xt[c][q]: bulk key, then final cost * 2^kb of cell (q, c)
-    __shared__ int32_t Ks[T][T + 1];  // bulk split, then final split
-    __shared__ double pJs[T + 1];     // p[col0 + q]
-
-    const int tid = threadIdx.x;
+    __shared__ CloseLds L;
     const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
     const TileChain ch = chains[sg.chain];
-    const int32_t n = ch.n, D = sg.D, P = sg.P, kb = ch.kb, kbits = ch.kbits;
+    const int local = blockIdx.x - sg.first;
+    const int tid = threadIdx.x;
+    const int32_t n = ch.n, D = sg.D, PT = sg.PT, kb = ch.kb, kbits = ch.kbits;
     int64_t *__restrict__ m = m_all + ch.m_off;
     int32_t *__restrict__ s = s_all + ch.s_off;
     const double *__restrict__ pd = pd_all + ch.pd_off;
     const uint64_t *__restrict__ part = part_all + sg.part_off;
-    const int I = blockIdx.x - sg.first, J = I + D;
+    const int I = local, J = I + D;
     const int row0 = I * T, col0 = J * T;
     const int nJ = min(T, n - col0);
     const double scale = ldexp(1.0, kb);
@@ -374,10 +387,10 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
         R.Xrow[t] = kPad;  // until cell (r, q) is final
     }
 
-    for (int q = tid; q <= T; q += CTH) pJs[q] = q <= nJ ? pd[col0 + q] : 0.0;
+    for (int q = tid; q <= T; q += CTH) L.pJs[q] = q <= nJ ? pd[col0 + q] : 0.0;
     for (int idx = tid; idx < T * CSTR; idx += CTH) {
-        (&DJt[0][0])[idx] = 0.0;
-        (&Xt[0][0])[idx] = 0.0;
+        (&L.DJt[0][0])[idx] = 0.0;
+        (&L.Xt[0][0])[idx] = 0.0;
     }
     __syncthreads();
     // DJ[q][c], 1 <= q <= c < nJ, read row-major (coalesced).
@@ -385,10 +398,10 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
     for (int idx = tid; idx < T * T; idx += CTH) {
         const int qq = idx / T, c = idx % T;
         if (qq >= 1 && qq <= c && c < nJ)
-            DJt[c][qq] = fma((double)m[(size_t)(col0 + qq) * n + col0 + c], scale,
-                             (double)(T + qq - 1));
+            L.DJt[c][qq] = fma((double)m[(size_t)(col0 + qq) * n + col0 + c], scale,
+                               (double)(T + qq - 1));
     }
-    // Bulk result per cell: the minimum of P packed (cost << kbits | k)
+    // Bulk result per cell: the minimum of the PT packed (cost << kbits | k)
     // partials, or for D == 1 the single bulk split k = (I+1)T-1 whose
     // operands both lie in the diagonal tiles.
     constexpr int CPT = T * T / CTH;  // cells per thread
@@ -401,7 +414,7 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
         for (int u = 0; u < CPT; ++u) {
             const int idx = tid + CTH * u;
             const int rr = idx / T, c = idx % T;
-            if (c < nJ) {
+            if (idx < T * T && c < nJ) {
                 const int64_t cost = m[(size_t)(row0 + rr) * n + k] +
                                      m[(size_t)(k + 1) * n + col0 + c] +
                                      (int64_t)pd[row0 + rr] * (int64_t)pd[k + 1] *
@@ -410,22 +423,38 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
             }
         }
     } else {
-        const uint64_t *src = part + ((size_t)I * P) * T * T + tid;
-        for (int ch = 0; ch < P; ++ch) {
-            uint64_t v[CPT];
+        const uint64_t *src = part + ((size_t)I * PT) * T * T;
+        int sl = 0;
+        for (; sl + 2 <= PT; sl += 2) {
+            uint64_t v0[CPT], v1[CPT];
 #pragma unroll
-            for (int u = 0; u < CPT; ++u) v[u] = src[(size_t)ch * T * T + CTH * u];
+            for (int u = 0; u < CPT; ++u) {
+                const int idx = tid + CTH * u;
+                v0[u] = idx < T * T ? src[(size_t)sl * T * T + idx] : UINT64_MAX;
+                v1[u] = idx < T * T ? src[(size_t)(sl + 1) * T * T + idx] : UINT64_MAX;
+            }
 #pragma unroll
-            for (int u = 0; u < CPT; ++u) key[u] = v[u] < key[u] ? v[u] : key[u];
+            for (int u = 0; u < CPT; ++u) {
+                const uint64_t w = v0[u] < v1[u] ? v0[u] : v1[u];
+                key[u] = w < key[u] ? w : key[u];
+            }
+        }
+        if (sl < PT) {
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                const int idx = tid + CTH * u;
+                const uint64_t w = idx < T * T ? src[(size_t)sl * T * T + idx] : UINT64_MAX;
+                key[u] = w < key[u] ? w : key[u];
+            }
         }
     }
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
         const int idx = tid + CTH * u;
         const int rr = idx / T, c = idx % T;
-        if (c < nJ) {
-            Xt[c][rr] = fma((double)(int64_t)(key[u] >> kbits), scale, (double)(T - 1));
-            Ks[rr][c] = (int32_t)(key[u] & kmask);
+        if (idx < T * T && c < nJ) {
+            L.Xt[c][rr] = fma((double)(int64_t)(key[u] >> kbits), scale, (double)(T - 1));
+            L.Ks[rr][c] = (int32_t)(key[u] & kmask);
         }
     }
     __syncthreads();
@@ -437,18 +466,14 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
         const int c_hi = c_lo + CROWS - 1;         // ... and of its last row
         if (c_hi >= 0 && c_lo < nJ) {              // wave-uniform
             const int cc = min(max(c, 0), nJ - 1);
-            const double pJc = pJs[cc + 1];
-            const double xbulk = Xt[cc][r];
+            const double pJc = L.pJs[cc + 1];
+            const double xbulk = L.Xt[cc][r];
             double best;
-            switch (h) {
-            case 0: best = close_step<0>(R, Xt, DJt, cc, g, pJc); break;
-            case 1: best = close_step<1>(R, Xt, DJt, cc, g, pJc); break;
-            case 2: best = close_step<2>(R, Xt, DJt, cc, g, pJc); break;
-            case 3: best = close_step<3>(R, Xt, DJt, cc, g, pJc); break;
-            case 4: best = close_step<4>(R, Xt, DJt, cc, g, pJc); break;
-            case 5: best = close_step<5>(R, Xt, DJt, cc, g, pJc); break;
-            case 6: best = close_step<6>(R, Xt, DJt, cc, g, pJc); break;
-            default: best = close_step<7>(R, Xt, DJt, cc, g, pJc); break;
+            switch ((h * CROWS) / CG) {  // wave-uniform first (a) slot
+            case 0: best = close_step<0>(R, L.Xt, L.DJt, cc, g, pJc); break;
+            case 1: best = close_step<1>(R, L.Xt, L.DJt, cc, g, pJc); break;
+            case 2: best = close_step<2>(R, L.Xt, L.DJt, cc, g, pJc); break;
+            default: best = close_step<3>(R, L.Xt, L.DJt, cc, g, pJc); break;
             }
             const double fin = fmin(best, xbulk);
             const double cost = floor(fin * inv_scale);
@@ -458,9 +483,9 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
                 for (int t = 0; t < CS; ++t)
                     if (t * CG + g == c) R.Xrow[t] = xv;
                 if (g == 0) {
-                    Xt[c][r] = xv;
+                    L.Xt[c][r] = xv;
                     const int kl = (int)fma(-cost, scale, fin);
-                    if (kl != T - 1) Ks[r][c] = kl < T - 1 ? row0 + kl : col0 + (kl - T);
+                    if (kl != T - 1) L.Ks[r][c] = kl < T - 1 ? row0 + kl : col0 + (kl - T);
                 }
             }
         }
@@ -471,42 +496,25 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
         const int rr = idx / T, c = idx % T;
         if (c < nJ) {
             const size_t o = (size_t)(row0 + rr) * n + col0 + c;
-            m[o] = (int64_t)(Xt[c][rr] * inv_scale);
-            s[o] = Ks[rr][c];
+            m[o] = (int64_t)(L.Xt[c][rr] * inv_scale);
+            s[o] = L.Ks[rr][c];
         }
     }
     for (int idx = tid; idx < T * T; idx += CTH) {
         const int c = idx / T, rr = idx % T;
         if (c < nJ) {
             const size_t o = (size_t)(col0 + c) * n + row0 + rr;
-            m[o] = (int64_t)(Xt[c][rr] * inv_scale);
+            m[o] = (int64_t)(L.Xt[c][rr] * inv_scale);
             s[o] = -1;
         }
     }
 }
 
-// Chunking of the bulk range of tile-diagonal D: P chunks of KS splits.
-// Aims at about 1024 workgroups per launch for a lone chain, at least 64
-// splits per chunk, at most 32 chunks per tile, and KS <= 2^kb so the fp64
-// key's split field holds every local index of a chunk.
-void bulk_split(int32_t NT, int32_t D, int32_t kb, int32_t *KS, int32_t *P)
-{
-    const int32_t tiles = NT - D;
-    const int32_t L = (D - 1) * T + 1;
-    const int32_t target_groups = 1024;
-    int32_t want = (target_groups + tiles - 1) / tiles;
-    int32_t maxp = (L + 63) / 64;
-    if (maxp > 32) maxp = 32;
-    if (want > maxp) want = maxp;
-    if (want < 1) want = 1;
-    int32_t ks = (L + want - 1) / want;
-    ks = (ks + KC - 1) / KC * KC;
-    const int32_t cap = kb >= 30 ? (1 << 30) : (1 << kb);
-    if (ks > cap) ks = cap / KC * KC;
-    *KS = ks;
-    *P = (L + ks - 1) / ks;
-}
+static_assert(CG == 16 && CS == 4 && CROWS == 4, "close_step dispatch assumes 4 slots");
 
+// ------------------------------------------------------------------------
+// Host planning.
+// ------------------------------------------------------------------------
 int32_t bitlen_u64(uint64_t v)
 {
     int32_t b = 0;
@@ -517,7 +525,6 @@ int32_t bitlen_u64(uint64_t v)
     return b;
 }
 
-// Split evaluations of one launch kind for chain c at tile-diagonal D.
 double tri_evals(int32_t n, int32_t NT)
 {
     double ev = 0.0;
@@ -528,13 +535,61 @@ double tri_evals(int32_t n, int32_t NT)
     return ev;
 }
 
+// Valid cells of the NT - D tiles of tile-diagonal D (the last tile column
+// may be ragged).
+double diag_cells(int32_t n, int32_t NT, int32_t D)
+{
+    const int32_t nlast = n - (NT - 1) * T;
+    return (double)(NT - D - 1) * T * T + (double)T * nlast;
+}
+
 }  // namespace
+
+BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone)
+{
+    BulkLayout bl{};
+    if (E < 2 || E >= NT) return bl;
+    const int32_t tiles = NT - E;
+    int32_t cap = kb >= 30 ? (1 << 30) : (1 << kb);
+    cap = cap / KC * KC;
+    // End blocks: E == 2 has a single range of T+1 splits, E >= 3 two of T.
+    const int32_t end_len = E == 2 ? T + 1 : T;
+    int32_t end_ks = lone ? 32 : 64;
+    if (end_ks > cap) end_ks = cap;
+    bl.end_ks = end_ks;
+    bl.end_nch = (end_len + end_ks - 1) / end_ks;
+    bl.n_end_ranges = E == 2 ? 1 : 2;
+    // Interior, E >= 3: (E-3)T + 1 splits.
+    if (E >= 3) {
+        const int32_t L = (E - 3) * T + 1;
+        int32_t want = 1;
+        if (lone) {
+            // A lone chain aims at about 1024 bulk units per launch, with
+            // at least 64 splits per chunk and at most 32 chunks per tile.
+            want = (1024 + tiles - 1) / tiles;
+            int32_t maxp = (L + 63) / 64;
+            if (maxp > 32) maxp = 32;
+            if (want > maxp) want = maxp;
+            if (want < 1) want = 1;
+        }
+        int32_t ks = (L + want - 1) / want;
+        ks = (ks + KC - 1) / KC * KC;
+        if (ks > cap) ks = cap;
+        bl.int_ks = ks;
+        bl.int_nch = (L + ks - 1) / ks;
+    }
+    bl.PT = bl.int_nch + bl.n_end_ranges * bl.end_nch;
+    bl.elems = (size_t)tiles * bl.PT * T * T;
+    return bl;
+}
 
 bool tiled_accepts(const ChainInfo &ci)
 {
     const int32_t kbits = bitlen_u64((uint64_t)(ci.n > 1 ? ci.n - 1 : 1));
     return ci.cost_bits + 7 <= 53 && ci.cost_bits + kbits <= 64;
 }
+
+int32_t tiled_nt(int32_t n) { return (n + T - 1) / T; }
 
 int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t s_off,
                    int64_t p_off, int64_t pd_off)
@@ -549,92 +604,159 @@ int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t 
     if (c.kb > 20) c.kb = 20;
     c.kbits = bitlen_u64((uint64_t)(ci.n > 1 ? ci.n - 1 : 1));
     plan.chains.push_back(c);
-    plan.NT.push_back((ci.n + T - 1) / T);
+    plan.NT.push_back(tiled_nt(ci.n));
     return (int)plan.chains.size() - 1;
 }
 
-void plan_add_iteration(TiledPlan &plan, const std::vector<int> &chain_ids,
-                        const std::vector<int> &Ds)
+void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
 {
+    auto push = [&](TiledLaunch L, int wait) {
+        L.wait = wait;
+        if (wait >= 0) plan.launches[wait].record = true;
+        plan.launches.push_back(L);
+        return (int)plan.launches.size() - 1;
+    };
+    // Diagonal tiles of chains starting now (main stream).
     TiledLaunch tri{TK_TRI, (int)plan.segs.size(), 0, 0, 0.0};
-    for (size_t u = 0; u < chain_ids.size(); ++u) {
-        const int c = chain_ids[u];
-        if (Ds[u] != 0) continue;
+    for (const ChainStep &cs : steps) {
+        if (cs.D != 0) continue;
         TileSeg sg{};
         sg.first = tri.blocks;
-        sg.chain = c;
-        sg.D = 0;
+        sg.chain = cs.chain;
         plan.segs.push_back(sg);
         tri.nseg += 1;
-        tri.blocks += plan.NT[c];
-        tri.evals += tri_evals(plan.chains[c].n, plan.NT[c]);
+        tri.blocks += plan.NT[cs.chain];
+        tri.evals += tri_evals(plan.chains[cs.chain].n, plan.NT[cs.chain]);
     }
-    if (tri.nseg) plan.launches.push_back(tri);
+    if (tri.nseg) push(tri, -1);
 
-    // Bulk and closure share each chain's partial buffer slice.
-    std::vector<int64_t> off(chain_ids.size(), 0);
-    std::vector<int32_t> KSv(chain_ids.size(), 0), Pv(chain_ids.size(), 0);
-    size_t used = 0;
-    for (size_t u = 0; u < chain_ids.size(); ++u) {
-        const int c = chain_ids[u], D = Ds[u];
-        if (D < 2 || D >= plan.NT[c]) continue;
-        bulk_split(plan.NT[c], D, plan.chains[c].kb, &KSv[u], &Pv[u]);
-        off[u] = (int64_t)used;
-        used += (size_t)(plan.NT[c] - D) * Pv[u] * T * T;
-    }
-    if (used > plan.part_elems) plan.part_elems = used;
-
-    TiledLaunch bulk{TK_BULK, (int)plan.segs.size(), 0, 0, 0.0};
-    for (size_t u = 0; u < chain_ids.size(); ++u) {
-        const int c = chain_ids[u], D = Ds[u];
-        if (D < 2 || D >= plan.NT[c]) continue;
-        const int32_t n = plan.chains[c].n, NT = plan.NT[c], tiles = NT - D;
-        TileSeg sg{};
-        sg.part_off = off[u];
-        sg.first = bulk.blocks;
-        sg.chain = c;
-        sg.D = D;
-        sg.P = Pv[u];
-        sg.KS = KSv[u];
-        plan.segs.push_back(sg);
-        bulk.nseg += 1;
-        bulk.blocks += tiles * Pv[u];
-        const int32_t nlast = n - (NT - 1) * T;
-        const double cells = (double)(tiles - 1) * T * T + (double)T * nlast;
-        bulk.evals += cells * ((double)(D - 1) * T + 1);
-    }
-    if (bulk.nseg) plan.launches.push_back(bulk);
-
+    // Closure of D (main stream), after the interior bulk of D (aux stream,
+    // previous iteration).
     TiledLaunch close{TK_CLOSE, (int)plan.segs.size(), 0, 0, 0.0};
-    for (size_t u = 0; u < chain_ids.size(); ++u) {
-        const int c = chain_ids[u], D = Ds[u];
-        if (D < 1 || D >= plan.NT[c]) continue;
-        const int32_t n = plan.chains[c].n, NT = plan.NT[c], tiles = NT - D;
+    for (const ChainStep &cs : steps) {
+        const int c = cs.chain, D = cs.D, NT = plan.NT[c];
+        if (D < 1 || D >= NT) continue;
+        const int32_t n = plan.chains[c].n;
+        const BulkLayout bl = bulk_layout(NT, D, plan.chains[c].kb, plan.lone);
         TileSeg sg{};
-        sg.part_off = off[u];
+        sg.part_off = cs.part_cur;
         sg.first = close.blocks;
         sg.chain = c;
         sg.D = D;
-        sg.P = Pv[u];
-        sg.KS = KSv[u];
+        sg.role = SEG_CLOSE;
+        sg.PT = bl.PT;
         plan.segs.push_back(sg);
         close.nseg += 1;
-        close.blocks += tiles;
+        close.blocks += NT - D;
         // (a) and (b) splits of every cell, plus the single bulk split of
         // D == 1: per tile sum over cells of (T-1-r) + c.
         const int32_t nlast = n - (NT - 1) * T;
         const double per_full = (double)T * T * (T - 1);
         const double per_last =
             (double)nlast * T * (T - 1) / 2.0 + (double)T * nlast * (nlast - 1) / 2.0;
-        double ev = (double)(tiles - 1) * per_full + per_last;
-        if (D == 1) ev += (double)(tiles - 1) * T * T + (double)T * nlast;
-        close.evals += ev;
+        close.evals += (double)(NT - D - 1) * per_full + per_last;
+        if (D == 1) close.evals += diag_cells(n, NT, D);
     }
-    if (close.nseg) plan.launches.push_back(close);
+    const int prev_close = plan.last_close;
+    if (close.nseg) plan.last_close = push(close, plan.last_interior);
+    plan.last_interior = -1;
+
+    auto add_bulk = [&](TiledLaunch &Lc, const ChainStep &cs, int E, int koff, int klen, int KS,
+                        int nch, int slot0, int PT) {
+        const int c = cs.chain, NT = plan.NT[c];
+        TileSeg sg{};
+        sg.part_off = cs.part_next;
+        sg.first = Lc.blocks;
+        sg.chain = c;
+        sg.D = E;
+        sg.role = SEG_BULK;
+        sg.KS = KS;
+        sg.nch = nch;
+        sg.koff = koff;
+        sg.klen = klen;
+        sg.slot0 = slot0;
+        sg.PT = PT;
+        plan.segs.push_back(sg);
+        Lc.nseg += 1;
+        Lc.blocks += (NT - E) * nch;
+        Lc.evals += diag_cells(plan.chains[c].n, NT, E) * klen;
+    };
+    // Interior bulk of D+1 (aux stream): needs tile-diagonals <= D-1 only,
+    // so it waits for the previous closure, not this one.
+    TiledLaunch inter{TK_BULK, (int)plan.segs.size(), 0, 0, 0.0};
+    inter.stream = 1;
+    for (const ChainStep &cs : steps) {
+        const int c = cs.chain, E = cs.D + 1, NT = plan.NT[c];
+        if (cs.D < 1 || E < 3 || E >= NT) continue;
+        const BulkLayout bl = bulk_layout(NT, E, plan.chains[c].kb, plan.lone);
+        add_bulk(inter, cs, E, T, (E - 3) * T + 1, bl.int_ks, bl.int_nch, 0, bl.PT);
+    }
+    if (inter.nseg) plan.last_interior = push(inter, prev_close);
+
+    // End blocks of D+1 (main stream, after the closure of D).
+    TiledLaunch ends{TK_BULK, (int)plan.segs.size(), 0, 0, 0.0};
+    for (const ChainStep &cs : steps) {
+        const int c = cs.chain, E = cs.D + 1, NT = plan.NT[c];
+        if (cs.D < 1 || E < 2 || E >= NT) continue;
+        const BulkLayout bl = bulk_layout(NT, E, plan.chains[c].kb, plan.lone);
+        if (E == 2) {
+            add_bulk(ends, cs, E, 0, T + 1, bl.end_ks, bl.end_nch, bl.int_nch, bl.PT);
+        } else {
+            add_bulk(ends, cs, E, 0, T, bl.end_ks, bl.end_nch, bl.int_nch, bl.PT);
+            add_bulk(ends, cs, E, (E - 2) * T + 1, T, bl.end_ks, bl.end_nch,
+                     bl.int_nch + bl.end_nch, bl.PT);
+        }
+    }
+    if (ends.nseg) push(ends, -1);
+}
+
+void plan_lockstep(TiledPlan &plan, const std::vector<int> &ids)
+{
+    // Two partial buffers, by parity of the tile-diagonal they hold.  In
+    // lockstep every chain with NT > E writes its layout of E in the
+    // iteration before E and reads it in iteration E, always in plan order,
+    // so positional offsets agree between writer and reader.
+    int maxNT = 0;
+    for (int c : ids) maxNT = plan.NT[c] > maxNT ? plan.NT[c] : maxNT;
+    auto offsets = [&](int E, std::vector<int64_t> &off) {
+        size_t used = 0;
+        off.assign(ids.size(), 0);
+        for (size_t u = 0; u < ids.size(); ++u) {
+            const int c = ids[u];
+            const BulkLayout bl = bulk_layout(plan.NT[c], E, plan.chains[c].kb, plan.lone);
+            off[u] = (int64_t)used;
+            used += bl.elems;
+        }
+        return used;
+    };
+    std::vector<int64_t> off;
+    size_t half = 0;
+    for (int E = 2; E < maxNT; ++E) {
+        const size_t used = offsets(E, off);
+        if (used > half) half = used;
+    }
+    plan.part_elems = 2 * half;
+    std::vector<int64_t> off_cur, off_next;
+    for (int D = 0; D < maxNT; ++D) {
+        offsets(D, off_cur);
+        offsets(D + 1, off_next);
+        std::vector<ChainStep> steps;
+        for (size_t u = 0; u < ids.size(); ++u) {
+            const int c = ids[u];
+            if (D >= plan.NT[c]) continue;
+            ChainStep cs;
+            cs.chain = c;
+            cs.D = D;
+            cs.part_cur = (int64_t)((D & 1) * half) + off_cur[u];
+            cs.part_next = (int64_t)(((D + 1) & 1) * half) + off_next[u];
+            steps.push_back(cs);
+        }
+        plan_add_iteration(plan, steps);
+    }
 }
 
 mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double *pd,
-                          int64_t *m_all, int32_t *s_all, hipStream_t stream)
+                          int64_t *m_all, int32_t *s_all, uint64_t *part_ext, hipStream_t stream)
 {
     if (plan.launches.empty()) return MCM_OK;
     // One device block: chain table, then segment table.
@@ -642,45 +764,84 @@ mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double 
     const size_t sbytes = plan.segs.size() * sizeof(TileSeg);
     const size_t soff = (cbytes + 255) / 256 * 256;
     void *tables = nullptr;
-    mcm_status st = upload_blob(stream, &tables, soff + sbytes,
-                                [&](char *dst) {
-                                    memcpy(dst, plan.chains.data(), cbytes);
-                                    memcpy(dst + soff, plan.segs.data(), sbytes);
-                                });
+    mcm_status st = upload_blob(stream, &tables, soff + sbytes, [&](char *dst) {
+        memcpy(dst, plan.chains.data(), cbytes);
+        memcpy(dst + soff, plan.segs.data(), sbytes);
+    });
     if (st != MCM_OK) return st;
     const TileChain *chains = (const TileChain *)tables;
     const TileSeg *segs = (const TileSeg *)((const char *)tables + soff);
-    uint64_t *part = nullptr;
-    if (plan.part_elems &&
-        ws_alloc((void **)&part, plan.part_elems * sizeof(uint64_t), stream) != hipSuccess) {
-        ws_free(tables, stream);
-        return MCM_ERR_NO_MEMORY;
-    }
-    for (const TiledLaunch &L : plan.launches) {
-        const TileSeg *sg = segs + L.seg_begin;
-        hipError_t e;
-        if (L.kind == TK_TRI) {
-            ProfileScope ps(KC_SETUP, stream, L.evals);
-            hipLaunchKernelGGL(k_tri, dim3(L.blocks), dim3(NTH), 0, stream, chains, sg, L.nseg,
-                               p, m_all, s_all);
-            e = hipGetLastError();
-        } else if (L.kind == TK_BULK) {
-            ProfileScope ps(KC_BULK, stream, L.evals);
-            hipLaunchKernelGGL(k_bulk, dim3(L.blocks), dim3(NTH), 0, stream, chains, sg, L.nseg,
-                               m_all, pd, part);
-            e = hipGetLastError();
-        } else {
-            ProfileScope ps(KC_CLOSE, stream, L.evals);
-            hipLaunchKernelGGL(k_close, dim3(L.blocks), dim3(CTH), 0, stream, chains, sg,
-                               L.nseg, m_all, s_all, pd, part);
-            e = hipGetLastError();
+    uint64_t *part = part_ext;
+    uint64_t *part_own = nullptr;
+    if (!part && plan.part_elems) {
+        if (ws_alloc((void **)&part_own, plan.part_elems * sizeof(uint64_t), stream) !=
+            hipSuccess) {
+            ws_free(tables, stream);
+            return MCM_ERR_NO_MEMORY;
         }
+        part = part_own;
+    }
+    bool uses_aux = false;
+    int nrec = 0;
+    for (const TiledLaunch &L : plan.launches) {
+        uses_aux |= L.stream == 1;
+        nrec += L.record ? 1 : 0;
+    }
+    // Events: one per launch another launch waits for, plus fork and join.
+    StreamPair sp;
+    if (uses_aux && acquire_stream_pair(stream, nrec + 2, &sp) != MCM_OK) st = MCM_ERR_DEVICE;
+    std::vector<hipEvent_t> rec(plan.launches.size(), nullptr);
+    int next_ev = 2;
+    bool forked = false;
+    if (uses_aux && st == MCM_OK) {
+        // Fork: the aux stream starts after everything already on `stream`
+        // (the tables upload, and earlier work of the caller).
+        if (hipEventRecord(sp.events[0], stream) != hipSuccess ||
+            hipStreamWaitEvent(sp.aux, sp.events[0], 0) != hipSuccess)
+            st = MCM_ERR_DEVICE;
+        forked = st == MCM_OK;
+    }
+    for (size_t li = 0; li < plan.launches.size() && st == MCM_OK; ++li) {
+        const TiledLaunch &L = plan.launches[li];
+        hipStream_t q = L.stream == 1 ? sp.aux : stream;
+        hipError_t e = hipSuccess;
+        if (L.wait >= 0 && plan.launches[L.wait].stream != L.stream)
+            e = hipStreamWaitEvent(q, rec[L.wait], 0);
         if (e != hipSuccess) {
             st = MCM_ERR_DEVICE;
             break;
         }
+        const TileSeg *sg = segs + L.seg_begin;
+        if (L.kind == TK_TRI) {
+            ProfileScope ps(KC_SETUP, q, L.evals);
+            hipLaunchKernelGGL(k_tri, dim3(L.blocks), dim3(NTH), 0, q, chains, sg, L.nseg, p,
+                               m_all, s_all);
+            e = hipGetLastError();
+        } else if (L.kind == TK_BULK) {
+            ProfileScope ps(KC_BULK, q, L.evals);
+            hipLaunchKernelGGL(k_bulk, dim3(L.blocks), dim3(NTH), 0, q, chains, sg, L.nseg,
+                               m_all, pd, part);
+            e = hipGetLastError();
+        } else {
+            ProfileScope ps(KC_CLOSE, q, L.evals);
+            hipLaunchKernelGGL(k_close, dim3(L.blocks), dim3(CTH), 0, q, chains, sg, L.nseg,
+                               m_all, s_all, pd, part);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess && L.record && uses_aux) {
+            rec[li] = sp.events[next_ev++];
+            e = hipEventRecord(rec[li], q);
+        }
+        if (e != hipSuccess) st = MCM_ERR_DEVICE;
     }
-    if (part) ws_free(part, stream);
+    if (forked) {
+        // Join: `stream` continues after everything enqueued on aux.
+        if (hipEventRecord(sp.events[1], sp.aux) != hipSuccess ||
+            hipStreamWaitEvent(stream, sp.events[1], 0) != hipSuccess)
+            st = MCM_ERR_DEVICE;
+    }
+    if (uses_aux) release_stream_pair(sp);
+    if (part_own) ws_free(part_own, stream);
     ws_free(tables, stream);
     return st;
 }
@@ -690,9 +851,10 @@ mcm_status run_tiled(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int
 {
     if (!tiled_accepts(ci)) return MCM_ERR_UNSUPPORTED;
     TiledPlan plan;
+    plan.lone = true;
     const int c = plan_add_chain(plan, ci, 0, 0, 0, 0);
-    for (int D = 0; D < plan.NT[c]; ++D) plan_add_iteration(plan, {c}, {D});
-    return run_tiled_plan(plan, dc.p, dc.pd, m, s, stream);
+    plan_lockstep(plan, {c});
+    return run_tiled_plan(plan, dc.p, dc.pd, m, s, nullptr, stream);
 }
 
 }  // namespace mcm

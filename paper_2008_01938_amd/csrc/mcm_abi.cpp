@@ -217,6 +217,47 @@ mcm_status upload_blob(hipStream_t stream, void **dev_out, size_t bytes,
     return MCM_OK;
 }
 
+namespace {
+std::mutex g_aux_mu;
+std::unordered_map<int, hipStream_t> g_aux;
+std::vector<hipEvent_t> g_event_pool;
+}  // namespace
+
+mcm_status acquire_stream_pair(hipStream_t main, int count, StreamPair *out)
+{
+    (void)main;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return MCM_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(g_aux_mu);
+    hipStream_t &aux = g_aux[device];
+    if (!aux && hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) {
+        aux = nullptr;
+        return MCM_ERR_DEVICE;
+    }
+    out->aux = aux;
+    out->events.clear();
+    while ((int)out->events.size() < count) {
+        hipEvent_t e = nullptr;
+        if (!g_event_pool.empty()) {
+            e = g_event_pool.back();
+            g_event_pool.pop_back();
+        } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            for (hipEvent_t x : out->events) g_event_pool.push_back(x);
+            out->events.clear();
+            return MCM_ERR_DEVICE;
+        }
+        out->events.push_back(e);
+    }
+    return MCM_OK;
+}
+
+void release_stream_pair(StreamPair &sp)
+{
+    std::lock_guard<std::mutex> lk(g_aux_mu);
+    for (hipEvent_t e : sp.events) g_event_pool.push_back(e);
+    sp.events.clear();
+}
+
 hipError_t ws_alloc(void **ptr, size_t bytes, hipStream_t stream)
 {
     return hipMallocAsync(ptr, bytes ? bytes : 1, stream);
@@ -376,8 +417,9 @@ mcm_status mcm_solve_batched(int32_t count, const int32_t *n, const int64_t *p_o
         ids.push_back(c);
         if (plan.NT[c] > maxNT) maxNT = plan.NT[c];
     }
-    for (int D = 0; D < maxNT; ++D) plan_add_iteration(plan, ids, std::vector<int>(ids.size(), D));
-    st = run_tiled_plan(plan, p_dev, pd_dev, m_all, s_all, stream);
+    (void)maxNT;
+    plan_lockstep(plan, ids);
+    st = run_tiled_plan(plan, p_dev, pd_dev, m_all, s_all, nullptr, stream);
     for (int32_t b = 0; b < count && st == MCM_OK; ++b) {
         if (tiled_accepts(ci[b])) continue;
         DeviceChain dc;

@@ -78,11 +78,18 @@ struct TileSeg {        // consecutive workgroups of one launch working on one c
     int32_t first;      // first workgroup index of the segment
     int32_t chain;      // index into the TileChain table
     int32_t D;          // tile-diagonal
-    int32_t P;          // bulk chunks per tile (0: no bulk partials)
-    int32_t KS;         // splits per bulk chunk
+    int32_t role;       // k_step: SEG_CLOSE or SEG_BULK
+    int32_t KS;         // bulk: splits per chunk
+    int32_t nch;        // bulk: chunks per tile in this range
+    int32_t groups;     // bulk: workgroups per tile (4 chunks each)
+    int32_t koff;       // bulk: range start, offset from (I+1)T-1
+    int32_t klen;       // bulk: range length
+    int32_t slot0;      // bulk: partial slot of the range's first chunk
+    int32_t PT;         // partial slots per tile (bulk: stride; closure: count)
     int32_t pad;
 };
 
+enum SegRole { SEG_CLOSE = 0, SEG_BULK = 1 };
 enum TiledKernel { TK_TRI = 0, TK_BULK = 1, TK_CLOSE = 2 };
 
 struct TiledLaunch {    // one kernel launch of a tiled plan
@@ -91,6 +98,30 @@ struct TiledLaunch {    // one kernel launch of a tiled plan
     int nseg;
     int blocks;         // workgroups
     double evals;       // split evaluations the launch performs
+    int stream = 0;     // 0: the caller's stream; 1: the library's aux stream
+    int wait = -1;      // launch (on the other stream) that must finish first
+    bool record = false;  // another launch waits for this one
+};
+
+// The library's second stream for a device, and events for one plan.
+struct StreamPair {
+    hipStream_t aux = nullptr;
+    std::vector<hipEvent_t> events;
+};
+// Aux stream of the current device and `count` events (timing disabled);
+// release returns the events once every wait on them has been enqueued.
+mcm_status acquire_stream_pair(hipStream_t main, int count, StreamPair *out);
+void release_stream_pair(StreamPair &sp);
+
+// Chunking of the bulk range of one tile-diagonal E of a chain: the
+// interior chunks fill partial slots [0, int_nch), the end-block chunks
+// the slots after them.
+struct BulkLayout {
+    int32_t int_ks = 0, int_nch = 0;       // interior: splits per chunk, chunks per tile
+    int32_t end_ks = 0, end_nch = 0;       // each end block: splits per chunk, chunks
+    int32_t n_end_ranges = 0;              // 1 (E == 2) or 2
+    int32_t PT = 0;                        // partial slots per tile
+    size_t elems = 0;                      // partial-minima elements (uint64) of all tiles
 };
 
 // Wavefront path (int64, any valid input).
@@ -109,20 +140,40 @@ struct TiledPlan {
     std::vector<TileSeg> segs;
     std::vector<TiledLaunch> launches;
     size_t part_elems = 0;             // partial-minima buffer (uint64) the plan needs
+    bool lone = false;                 // one chain: cut bulk ranges finely to fill the GPU
+    int last_close = -1;               // latest closure launch
+    int last_interior = -1;            // latest interior-bulk launch (aux stream)
 };
 
+// One chain's place in an iteration: it advances from tile-diagonal D to
+// D+1.  part_cur: offset of the partial minima of D (read by the closure);
+// part_next: offset of those of D+1 (written by its bulk).
+struct ChainStep {
+    int chain = 0;
+    int D = 0;
+    int64_t part_cur = 0;
+    int64_t part_next = 0;
+};
+
+int32_t tiled_nt(int32_t n);
+BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone);
 // Add a chain (offsets as in TileChain); returns its index.
 int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t s_off,
                    int64_t p_off, int64_t pd_off);
 // Append one iteration: each listed chain advances by one tile-diagonal
-// (D = 0 runs its diagonal tiles; D >= 1 its bulk and closure).  Chains
-// with D >= NT are skipped.  Launches: diagonal tiles, bulk, closure.
-void plan_add_iteration(TiledPlan &plan, const std::vector<int> &chain_ids,
-                        const std::vector<int> &Ds);
+// (D = 0 runs its diagonal tiles; D >= 1 closes D and computes the bulk of
+// D+1).  Launches: diagonal tiles, closure of D, interior bulk of D+1 (aux
+// stream, concurrent with the closure), end blocks of D+1.
+void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps);
+// All chains advance together from D = 0 to their last tile-diagonal, with
+// partial minima in one plan-owned buffer (plan.part_elems).
+void plan_lockstep(TiledPlan &plan, const std::vector<int> &ids);
 // Execute a plan on `stream`: p (int32) and pd (fp64) hold every chain's
 // dimensions at its p_off / pd_off; m_all / s_all its tables at m_off /
-// s_off.
+// s_off.  part_ext: base of the partial minima, or NULL for a buffer of
+// plan.part_elems allocated here.
 mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double *pd,
-                          int64_t *m_all, int32_t *s_all, hipStream_t stream);
+                          int64_t *m_all, int32_t *s_all, uint64_t *part_ext,
+                          hipStream_t stream);
 
 }  // namespace mcm

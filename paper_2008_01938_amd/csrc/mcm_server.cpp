@@ -86,8 +86,11 @@ struct Request {
     std::vector<int32_t> p;
     bool tiled = false;
     int NT = 0, D = 0;
-    // Arena block: [p int32 | pd fp64 | m int64 | s int32], each aligned.
-    size_t off = SIZE_MAX, bytes = 0, p_at = 0, pd_at = 0, m_at = 0, s_at = 0;
+    // Arena block: [p int32 | pd fp64 | m int64 | s int32 | partial minima],
+    // each aligned.  The partial region holds two tile-diagonals (by parity)
+    // of part_half uint64 each.
+    size_t off = SIZE_MAX, bytes = 0, p_at = 0, pd_at = 0, m_at = 0, s_at = 0, part_at = 0;
+    size_t part_half = 0;
     int32_t status = MCM_OK;
     double t_submit = 0, t_admit = 0, t_done = 0;
 };
@@ -99,7 +102,17 @@ void layout(Request &r)
     r.pd_at = align_up(np * sizeof(int32_t));
     r.m_at = r.pd_at + align_up(np * sizeof(double));
     r.s_at = r.m_at + align_up(nn * sizeof(int64_t));
-    r.bytes = r.s_at + align_up(nn * sizeof(int32_t));
+    r.part_at = r.s_at + align_up(nn * sizeof(int32_t));
+    r.part_half = 0;
+    if (r.tiled) {
+        int32_t kb = 53 - r.ci.cost_bits;
+        if (kb > 20) kb = 20;
+        for (int E = 2; E < r.NT; ++E) {
+            const BulkLayout bl = bulk_layout(r.NT, E, kb, false);
+            if (bl.elems > r.part_half) r.part_half = bl.elems;
+        }
+    }
+    r.bytes = r.part_at + align_up(2 * r.part_half * sizeof(uint64_t));
 }
 
 struct Inflight {
@@ -173,19 +186,23 @@ bool Server::launch_iteration()
         });
     }
     TiledPlan plan;
-    std::vector<int> ids, Ds;
+    std::vector<ChainStep> steps;
     for (Request *r : batch) {
         if (!r->tiled) continue;
-        const int c = plan_add_chain(plan, r->ci, (int64_t)((r->off + r->m_at) / sizeof(int64_t)),
-                                     (int64_t)((r->off + r->s_at) / sizeof(int32_t)),
-                                     (int64_t)((r->off + r->p_at) / sizeof(int32_t)),
-                                     (int64_t)((r->off + r->pd_at) / sizeof(double)));
-        ids.push_back(c);
-        Ds.push_back(r->D);
+        ChainStep cs;
+        cs.chain = plan_add_chain(plan, r->ci, (int64_t)((r->off + r->m_at) / sizeof(int64_t)),
+                                  (int64_t)((r->off + r->s_at) / sizeof(int32_t)),
+                                  (int64_t)((r->off + r->p_at) / sizeof(int32_t)),
+                                  (int64_t)((r->off + r->pd_at) / sizeof(double)));
+        cs.D = r->D;
+        const int64_t part0 = (int64_t)((r->off + r->part_at) / sizeof(uint64_t));
+        cs.part_cur = part0 + (int64_t)((r->D & 1) * r->part_half);
+        cs.part_next = part0 + (int64_t)(((r->D + 1) & 1) * r->part_half);
+        steps.push_back(cs);
     }
-    if (st == MCM_OK && !ids.empty()) {
-        plan_add_iteration(plan, ids, Ds);
-        st = run_tiled_plan(plan, p_i32, p_f64, m_i64, s_i32, stream);
+    if (st == MCM_OK && !steps.empty()) {
+        plan_add_iteration(plan, steps);
+        st = run_tiled_plan(plan, p_i32, p_f64, m_i64, s_i32, (uint64_t *)arena_dev, stream);
     }
     for (Request *r : batch) {
         if (r->tiled || st != MCM_OK) continue;
@@ -321,7 +338,7 @@ mcm_status mcm_server_submit(mcm_server *srv, const int32_t *p, int32_t n, uint6
     r->ci = ci;
     r->p.assign(p, p + n + 1);
     r->tiled = tiled_accepts(ci);
-    r->NT = (n + 63) / 64;
+    r->NT = tiled_nt(n);
     layout(*r);
     if (align_up(r->bytes) > srv->budget) {
         delete r;
@@ -358,6 +375,18 @@ mcm_status mcm_server_poll(mcm_server *srv, mcm_request_info *out, int32_t cap, 
     }
     *count = k;
     return MCM_OK;
+}
+
+size_t mcm_server_request_bytes(const int32_t *p, int32_t n)
+{
+    ChainInfo ci;
+    if (check_chain(p, n, &ci) != MCM_OK) return 0;
+    Request r;
+    r.ci = ci;
+    r.tiled = tiled_accepts(ci);
+    r.NT = tiled_nt(n);
+    layout(r);
+    return align_up(r.bytes);
 }
 
 mcm_status mcm_server_release(mcm_server *srv, uint64_t tag)

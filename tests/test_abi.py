@@ -142,3 +142,12 @@ def test_batched_rejects_bad_input_before_device(lib):
     assert call([2], [0], [3, 4, 5], [0], count=-1) == binding.ERR_INVALID_ARG
     assert call([], [], [], [], count=0) == binding.OK                             # no-op
     assert np.all(m == 7) and np.all(s == 7)
+
+
+def test_server_request_bytes(lib):
+    assert binding.server_request_bytes([3, 0, 4]) == 0
+    small = binding.server_request_bytes([3, 4, 5])
+    big = binding.server_request_bytes(np.full(1001, 7, dtype=np.int32))
+    # dims, m (8 B) and s (4 B) tables at least, 256-byte aligned
+    assert small >= 2 * 2 * 12 and small % 256 == 0
+    assert big >= 1000 * 1000 * 12 and big > small

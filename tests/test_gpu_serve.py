@@ -47,8 +47,8 @@ def test_served_equals_alone_and_oracle():
 
 def test_tiny_budget_forces_queueing():
     st = small_stream(30, rate=1e6, seed=5, n_hi=400)     # all arrive at once
-    nmax = int(st.batch.ns.max())
-    budget = nmax * nmax * 12 + 64 * 1024                 # about one request at a time
+    need = [binding.server_request_bytes(st.batch.dims(i)) for i in range(30)]
+    budget = max(need) + 4096                             # about one request at a time
     _say(f"[gpu] serve with budget {budget} bytes")
     res = serve.run_served(st, mem_budget=budget, max_slots=64, keep=range(30))
     for i in range(30):
