@@ -42,6 +42,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+#include <unordered_map>
+
 #include "mcm_internal.h"
 
 namespace mcm {
@@ -304,8 +307,8 @@ __device__ __forceinline__ double dpp_perm(double v)
 {
     const int2 b = __builtin_bit_cast(int2, v);
     int2 o;
-    o.x = __builtin_amdgcn_update_dpp(0, b.x, CTRL, 0xF, 0xF, false);
-    o.y = __builtin_amdgcn_update_dpp(0, b.y, CTRL, 0xF, 0xF, false);
+    o.x = __builtin_amdgcn_mov_dpp(b.x, CTRL, 0xF, 0xF, false);
+    o.y = __builtin_amdgcn_mov_dpp(b.y, CTRL, 0xF, 0xF, false);
     return __builtin_bit_cast(double, o);
 }
 
@@ -459,6 +462,9 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
     }
     __syncthreads();
 
+    // The sweep is the critical path of the solve; bulk workgroups sharing
+    // the CU fill the issue slots it leaves idle.
+    __builtin_amdgcn_s_setprio(3);
     const int wmax = (T - 1) + (nJ - 1);
     for (int w = 0; w <= wmax; ++w) {
         const int c = w - (T - 1 - r);
@@ -512,6 +518,31 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
 
 static_assert(CG == 16 && CS == 4 && CROWS == 4, "close_step dispatch assumes 4 slots");
 
+// Dynamic LDS requested on top of CloseLds by every closure launch, so that
+// no bulk workgroup fits beside a closure workgroup on a CU (160 KB per CU):
+// the closure's sweep is latency-bound and slows down several-fold next to
+// a bulk workgroup.
+constexpr size_t kCloseExtraLds = 163840 - sizeof(CloseLds) - sizeof(BulkLds) + 1024;
+static_assert(sizeof(CloseLds) + kCloseExtraLds <= 163840, "closure LDS exceeds a CU");
+
+// A bounded pause (constant-rate wall clock) on the stream it runs on.
+__global__ __launch_bounds__(64) void k_delay(long long ticks)
+{
+    const long long t0 = wall_clock64();
+    while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(8);
+}
+
+// Ticks of the pause before an interior bulk launch: about 4 microseconds.
+long long delay_ticks_for_device()
+{
+    int device = 0, khz = 0;
+    if (hipGetDevice(&device) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess ||
+        khz <= 0)
+        khz = 100000;
+    return (long long)khz * 4 / 1000;
+}
+
 // ------------------------------------------------------------------------
 // Host planning.
 // ------------------------------------------------------------------------
@@ -545,35 +576,72 @@ double diag_cells(int32_t n, int32_t NT, int32_t D)
 
 }  // namespace
 
-BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone)
+namespace {
+// Estimated duration, in split units, of `units` equal workgroups of `ks`
+// splits each on `slots` resident workgroup slots: whole waves of
+// workgroups, each paying about one staged round of fixed cost.
+double wave_cost(int64_t units, int32_t ks, int64_t slots)
+{
+    const int64_t waves = (units + slots - 1) / slots;
+    return (double)waves * (double)(ks + KC);
+}
+
+}  // namespace
+
+BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus, int slots_per_cu)
 {
     BulkLayout bl{};
     if (E < 2 || E >= NT) return bl;
     const int32_t tiles = NT - E;
     int32_t cap = kb >= 30 ? (1 << 30) : (1 << kb);
     cap = cap / KC * KC;
+    const bool fit = lone && cus >= 64 && slots_per_cu > 0;
+    int64_t slots_int = 0, slots_end = 0;
+    if (fit) {
+        // The closure of E-1 holds one CU per tile (NT-E+1) while the
+        // interior runs; the end blocks follow the closure on those CUs.
+        int64_t held = NT - E + 1;
+        if (held > cus - cus / 4) held = cus - cus / 4;
+        slots_int = (int64_t)slots_per_cu * (cus - held);
+        slots_end = (int64_t)slots_per_cu * held;
+    }
     // End blocks: E == 2 has a single range of T+1 splits, E >= 3 two of T.
     const int32_t end_len = E == 2 ? T + 1 : T;
-    int32_t end_ks = lone ? 32 : 64;
+    bl.n_end_ranges = E == 2 ? 1 : 2;
+    int32_t end_ks = 64;
+    if (fit) {
+        double best = 0.0;
+        for (int32_t ks = KC; ks <= end_len + KC - 1; ks += KC) {
+            const int32_t nch = (end_len + ks - 1) / ks;
+            const double c = wave_cost((int64_t)tiles * bl.n_end_ranges * nch, ks, slots_end);
+            if (ks == KC || c < best) {
+                best = c;
+                end_ks = ks;
+            }
+        }
+    }
     if (end_ks > cap) end_ks = cap;
     bl.end_ks = end_ks;
     bl.end_nch = (end_len + end_ks - 1) / end_ks;
-    bl.n_end_ranges = E == 2 ? 1 : 2;
     // Interior, E >= 3: (E-3)T + 1 splits.
     if (E >= 3) {
         const int32_t L = (E - 3) * T + 1;
-        int32_t want = 1;
-        if (lone) {
-            // A lone chain aims at about 1024 bulk units per launch, with
-            // at least 64 splits per chunk and at most 32 chunks per tile.
-            want = (1024 + tiles - 1) / tiles;
-            int32_t maxp = (L + 63) / 64;
-            if (maxp > 32) maxp = 32;
-            if (want > maxp) want = maxp;
-            if (want < 1) want = 1;
+        int32_t ks = (L + KC - 1) / KC * KC;
+        if (fit) {
+            // Chunks per tile (at most 32 partial slots) that minimise the
+            // estimated duration on the interior's slots.
+            double best = 0.0;
+            for (int32_t want = 1; want <= 32 && (want - 1) * KC < L; ++want) {
+                int32_t k = (L + want - 1) / want;
+                k = (k + KC - 1) / KC * KC;
+                const int32_t nch = (L + k - 1) / k;
+                const double c = wave_cost((int64_t)tiles * nch, k, slots_int);
+                if (want == 1 || c < best) {
+                    best = c;
+                    ks = k;
+                }
+            }
         }
-        int32_t ks = (L + want - 1) / want;
-        ks = (ks + KC - 1) / KC * KC;
         if (ks > cap) ks = cap;
         bl.int_ks = ks;
         bl.int_nch = (L + ks - 1) / ks;
@@ -581,6 +649,20 @@ BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone)
     bl.PT = bl.int_nch + bl.n_end_ranges * bl.end_nch;
     bl.elems = (size_t)tiles * bl.PT * T * T;
     return bl;
+}
+
+int bulk_blocks_per_cu()
+{
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return 0;
+    static std::mutex mu;
+    static std::unordered_map<int, int> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    int &nb = cache[device];
+    if (nb == 0 && hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bulk, NTH, 0) !=
+                       hipSuccess)
+        nb = 0;
+    return nb;
 }
 
 bool tiled_accepts(const ChainInfo &ci)
@@ -614,7 +696,10 @@ void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
         L.wait = wait;
         if (wait >= 0) plan.launches[wait].record = true;
         plan.launches.push_back(L);
-        return (int)plan.launches.size() - 1;
+        const int idx = (int)plan.launches.size() - 1;
+        if (L.stream == 0) plan.last_main = idx;
+        else plan.uses_aux = true;
+        return idx;
     };
     // Diagonal tiles of chains starting now (main stream).
     TiledLaunch tri{TK_TRI, (int)plan.segs.size(), 0, 0, 0.0};
@@ -637,7 +722,7 @@ void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
         const int c = cs.chain, D = cs.D, NT = plan.NT[c];
         if (D < 1 || D >= NT) continue;
         const int32_t n = plan.chains[c].n;
-        const BulkLayout bl = bulk_layout(NT, D, plan.chains[c].kb, plan.lone);
+        const BulkLayout bl = bulk_layout(NT, D, plan.chains[c].kb, plan.lone, plan.cus, plan.slots_per_cu);
         TileSeg sg{};
         sg.part_off = cs.part_cur;
         sg.first = close.blocks;
@@ -657,7 +742,9 @@ void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
         close.evals += (double)(NT - D - 1) * per_full + per_last;
         if (D == 1) close.evals += diag_cells(n, NT, D);
     }
-    const int prev_close = plan.last_close;
+    // The interior bulk of D+1 needs the closure of D-1, complete once the
+    // launches before this closure on the caller's stream are.
+    const int before_close = plan.last_main;
     if (close.nseg) plan.last_close = push(close, plan.last_interior);
     plan.last_interior = -1;
 
@@ -688,17 +775,25 @@ void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
     for (const ChainStep &cs : steps) {
         const int c = cs.chain, E = cs.D + 1, NT = plan.NT[c];
         if (cs.D < 1 || E < 3 || E >= NT) continue;
-        const BulkLayout bl = bulk_layout(NT, E, plan.chains[c].kb, plan.lone);
+        const BulkLayout bl = bulk_layout(NT, E, plan.chains[c].kb, plan.lone, plan.cus, plan.slots_per_cu);
         add_bulk(inter, cs, E, T, (E - 3) * T + 1, bl.int_ks, bl.int_nch, 0, bl.PT);
     }
-    if (inter.nseg) plan.last_interior = push(inter, prev_close);
+    if (inter.nseg) {
+        // A short pause on the aux stream lets the closure's workgroups
+        // reach their CUs first: a closure workgroup needs a CU of its own,
+        // and interior workgroups dispatched earlier would hold them all.
+        TiledLaunch delay{TK_DELAY, 0, 0, 1, 0.0};
+        delay.stream = 1;
+        push(delay, before_close);
+        plan.last_interior = push(inter, -1);
+    }
 
     // End blocks of D+1 (main stream, after the closure of D).
     TiledLaunch ends{TK_BULK, (int)plan.segs.size(), 0, 0, 0.0};
     for (const ChainStep &cs : steps) {
         const int c = cs.chain, E = cs.D + 1, NT = plan.NT[c];
         if (cs.D < 1 || E < 2 || E >= NT) continue;
-        const BulkLayout bl = bulk_layout(NT, E, plan.chains[c].kb, plan.lone);
+        const BulkLayout bl = bulk_layout(NT, E, plan.chains[c].kb, plan.lone, plan.cus, plan.slots_per_cu);
         if (E == 2) {
             add_bulk(ends, cs, E, 0, T + 1, bl.end_ks, bl.end_nch, bl.int_nch, bl.PT);
         } else {
@@ -723,7 +818,8 @@ void plan_lockstep(TiledPlan &plan, const std::vector<int> &ids)
         off.assign(ids.size(), 0);
         for (size_t u = 0; u < ids.size(); ++u) {
             const int c = ids[u];
-            const BulkLayout bl = bulk_layout(plan.NT[c], E, plan.chains[c].kb, plan.lone);
+            const BulkLayout bl = bulk_layout(plan.NT[c], E, plan.chains[c].kb, plan.lone, plan.cus,
+                                                plan.slots_per_cu);
             off[u] = (int64_t)used;
             used += bl.elems;
         }
@@ -781,29 +877,27 @@ mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double 
         }
         part = part_own;
     }
-    bool uses_aux = false;
     int nrec = 0;
-    for (const TiledLaunch &L : plan.launches) {
-        uses_aux |= L.stream == 1;
-        nrec += L.record ? 1 : 0;
-    }
+    for (const TiledLaunch &L : plan.launches) nrec += L.record ? 1 : 0;
+    const bool aux = plan.uses_aux;
     // Events: one per launch another launch waits for, plus fork and join.
-    StreamPair sp;
-    if (uses_aux && acquire_stream_pair(stream, nrec + 2, &sp) != MCM_OK) st = MCM_ERR_DEVICE;
+    StreamSet ss;
+    if (aux && acquire_streams(nrec + 2, &ss) != MCM_OK) st = MCM_ERR_DEVICE;
     std::vector<hipEvent_t> rec(plan.launches.size(), nullptr);
     int next_ev = 2;
     bool forked = false;
-    if (uses_aux && st == MCM_OK) {
+    if (aux && st == MCM_OK) {
         // Fork: the aux stream starts after everything already on `stream`
         // (the tables upload, and earlier work of the caller).
-        if (hipEventRecord(sp.events[0], stream) != hipSuccess ||
-            hipStreamWaitEvent(sp.aux, sp.events[0], 0) != hipSuccess)
+        if (hipEventRecord(ss.events[0], stream) != hipSuccess ||
+            hipStreamWaitEvent(ss.aux, ss.events[0], 0) != hipSuccess)
             st = MCM_ERR_DEVICE;
         forked = st == MCM_OK;
     }
+    const long long delay_ticks = aux ? delay_ticks_for_device() : 0;
     for (size_t li = 0; li < plan.launches.size() && st == MCM_OK; ++li) {
         const TiledLaunch &L = plan.launches[li];
-        hipStream_t q = L.stream == 1 ? sp.aux : stream;
+        hipStream_t q = L.stream == 1 ? ss.aux : stream;
         hipError_t e = hipSuccess;
         if (L.wait >= 0 && plan.launches[L.wait].stream != L.stream)
             e = hipStreamWaitEvent(q, rec[L.wait], 0);
@@ -822,25 +916,28 @@ mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double 
             hipLaunchKernelGGL(k_bulk, dim3(L.blocks), dim3(NTH), 0, q, chains, sg, L.nseg,
                                m_all, pd, part);
             e = hipGetLastError();
-        } else {
+        } else if (L.kind == TK_CLOSE) {
             ProfileScope ps(KC_CLOSE, q, L.evals);
-            hipLaunchKernelGGL(k_close, dim3(L.blocks), dim3(CTH), 0, q, chains, sg, L.nseg,
-                               m_all, s_all, pd, part);
+            hipLaunchKernelGGL(k_close, dim3(L.blocks), dim3(CTH), kCloseExtraLds, q, chains, sg,
+                               L.nseg, m_all, s_all, pd, part);
+            e = hipGetLastError();
+        } else {
+            hipLaunchKernelGGL(k_delay, dim3(1), dim3(64), 0, q, delay_ticks);
             e = hipGetLastError();
         }
-        if (e == hipSuccess && L.record && uses_aux) {
-            rec[li] = sp.events[next_ev++];
+        if (e == hipSuccess && L.record && aux) {
+            rec[li] = ss.events[next_ev++];
             e = hipEventRecord(rec[li], q);
         }
         if (e != hipSuccess) st = MCM_ERR_DEVICE;
     }
     if (forked) {
         // Join: `stream` continues after everything enqueued on aux.
-        if (hipEventRecord(sp.events[1], sp.aux) != hipSuccess ||
-            hipStreamWaitEvent(stream, sp.events[1], 0) != hipSuccess)
+        if (hipEventRecord(ss.events[1], ss.aux) != hipSuccess ||
+            hipStreamWaitEvent(stream, ss.events[1], 0) != hipSuccess)
             st = MCM_ERR_DEVICE;
     }
-    if (uses_aux) release_stream_pair(sp);
+    if (aux) release_streams(ss);
     if (part_own) ws_free(part_own, stream);
     ws_free(tables, stream);
     return st;
@@ -852,6 +949,8 @@ mcm_status run_tiled(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int
     if (!tiled_accepts(ci)) return MCM_ERR_UNSUPPORTED;
     TiledPlan plan;
     plan.lone = true;
+    plan.cus = device_cus();
+    plan.slots_per_cu = bulk_blocks_per_cu();
     const int c = plan_add_chain(plan, ci, 0, 0, 0, 0);
     plan_lockstep(plan, {c});
     return run_tiled_plan(plan, dc.p, dc.pd, m, s, nullptr, stream);

@@ -218,17 +218,31 @@ mcm_status upload_blob(hipStream_t stream, void **dev_out, size_t bytes,
 }
 
 namespace {
-std::mutex g_aux_mu;
+// Library aux streams and pooled events, per device.  Streams live until
+// the process ends.
+std::mutex g_streams_mu;
 std::unordered_map<int, hipStream_t> g_aux;
-std::vector<hipEvent_t> g_event_pool;
+std::unordered_map<int, std::vector<hipEvent_t>> g_event_pool;
+std::unordered_map<int, int> g_cus;
 }  // namespace
 
-mcm_status acquire_stream_pair(hipStream_t main, int count, StreamPair *out)
+int device_cus()
 {
-    (void)main;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(g_streams_mu);
+    int &n = g_cus[device];
+    if (n == 0 && hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) !=
+                      hipSuccess)
+        n = 0;
+    return n;
+}
+
+mcm_status acquire_streams(int count, StreamSet *out)
+{
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return MCM_ERR_DEVICE;
-    std::lock_guard<std::mutex> lk(g_aux_mu);
+    std::lock_guard<std::mutex> lk(g_streams_mu);
     hipStream_t &aux = g_aux[device];
     if (!aux && hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) {
         aux = nullptr;
@@ -236,13 +250,14 @@ mcm_status acquire_stream_pair(hipStream_t main, int count, StreamPair *out)
     }
     out->aux = aux;
     out->events.clear();
+    std::vector<hipEvent_t> &pool = g_event_pool[device];
     while ((int)out->events.size() < count) {
         hipEvent_t e = nullptr;
-        if (!g_event_pool.empty()) {
-            e = g_event_pool.back();
-            g_event_pool.pop_back();
+        if (!pool.empty()) {
+            e = pool.back();
+            pool.pop_back();
         } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-            for (hipEvent_t x : out->events) g_event_pool.push_back(x);
+            for (hipEvent_t x : out->events) pool.push_back(x);
             out->events.clear();
             return MCM_ERR_DEVICE;
         }
@@ -251,11 +266,14 @@ mcm_status acquire_stream_pair(hipStream_t main, int count, StreamPair *out)
     return MCM_OK;
 }
 
-void release_stream_pair(StreamPair &sp)
+void release_streams(StreamSet &ss)
 {
-    std::lock_guard<std::mutex> lk(g_aux_mu);
-    for (hipEvent_t e : sp.events) g_event_pool.push_back(e);
-    sp.events.clear();
+    int device = 0;
+    (void)hipGetDevice(&device);
+    std::lock_guard<std::mutex> lk(g_streams_mu);
+    std::vector<hipEvent_t> &pool = g_event_pool[device];
+    for (hipEvent_t e : ss.events) pool.push_back(e);
+    ss.events.clear();
 }
 
 hipError_t ws_alloc(void **ptr, size_t bytes, hipStream_t stream)

@@ -90,7 +90,7 @@ struct TileSeg {        // consecutive workgroups of one launch working on one c
 };
 
 enum SegRole { SEG_CLOSE = 0, SEG_BULK = 1 };
-enum TiledKernel { TK_TRI = 0, TK_BULK = 1, TK_CLOSE = 2 };
+enum TiledKernel { TK_TRI = 0, TK_BULK = 1, TK_CLOSE = 2, TK_DELAY = 3 };
 
 struct TiledLaunch {    // one kernel launch of a tiled plan
     int kind;           // TiledKernel
@@ -99,23 +99,29 @@ struct TiledLaunch {    // one kernel launch of a tiled plan
     int blocks;         // workgroups
     double evals;       // split evaluations the launch performs
     int stream = 0;     // 0: the caller's stream; 1: the library's aux stream
-    int wait = -1;      // launch (on the other stream) that must finish first
+    int wait = -1;      // launch (on another stream) that must finish first
     bool record = false;  // another launch waits for this one
 };
 
-// The library's second stream for a device, and events for one plan.
-struct StreamPair {
+// The library's second stream on the current device (non-blocking, default
+// priority, created once) and `count` events (timing disabled) from a pool.
+struct StreamSet {
     hipStream_t aux = nullptr;
     std::vector<hipEvent_t> events;
 };
-// Aux stream of the current device and `count` events (timing disabled);
-// release returns the events once every wait on them has been enqueued.
-mcm_status acquire_stream_pair(hipStream_t main, int count, StreamPair *out);
-void release_stream_pair(StreamPair &sp);
+mcm_status acquire_streams(int count, StreamSet *out);
+// Returns the events once every wait on them has been enqueued.
+void release_streams(StreamSet &ss);
+// Compute units of the current device, and resident k_bulk workgroups per CU.
+int device_cus();
+int bulk_blocks_per_cu();
 
 // Chunking of the bulk range of one tile-diagonal E of a chain: the
 // interior chunks fill partial slots [0, int_nch), the end-block chunks
-// the slots after them.
+// the slots after them.  For a lone chain the chunk counts are fitted to
+// the workgroup slots the launch finds free: the interior runs beside the
+// closure of E-1, which holds NT-E+1 CUs; the end blocks run on those CUs
+// after it.
 struct BulkLayout {
     int32_t int_ks = 0, int_nch = 0;       // interior: splits per chunk, chunks per tile
     int32_t end_ks = 0, end_nch = 0;       // each end block: splits per chunk, chunks
@@ -140,7 +146,11 @@ struct TiledPlan {
     std::vector<TileSeg> segs;
     std::vector<TiledLaunch> launches;
     size_t part_elems = 0;             // partial-minima buffer (uint64) the plan needs
-    bool lone = false;                 // one chain: cut bulk ranges finely to fill the GPU
+    bool lone = false;                 // one chain: fit bulk chunks to the GPU's slots
+    int cus = 0;                       // lone: compute units of the device
+    int slots_per_cu = 0;              // lone: resident k_bulk workgroups per CU
+    bool uses_aux = false;             // some launch runs on the aux stream
+    int last_main = -1;                // latest launch on the caller's stream
     int last_close = -1;               // latest closure launch
     int last_interior = -1;            // latest interior-bulk launch (aux stream)
 };
@@ -156,7 +166,9 @@ struct ChainStep {
 };
 
 int32_t tiled_nt(int32_t n);
-BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone);
+// lone: cus / slots_per_cu describe the device (TiledPlan); else ignored.
+BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus = 0,
+                       int slots_per_cu = 0);
 // Add a chain (offsets as in TileChain); returns its index.
 int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t s_off,
                    int64_t p_off, int64_t pd_off);
