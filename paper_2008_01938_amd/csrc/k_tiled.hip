@@ -580,6 +580,11 @@ namespace {
 // Estimated duration, in split units, of `units` equal workgroups of `ks`
 // splits each on `slots` resident workgroup slots: whole waves of
 // workgroups, each paying about one staged round of fixed cost.
+// Duration of a lone chain's closure in split times of a bulk workgroup
+// (a closure sweep takes about as long as a resident bulk workgroup needs
+// for this many splits).
+constexpr int32_t kCloseSplits = 256;
+
 double wave_cost(int64_t units, int32_t ks, int64_t slots)
 {
     const int64_t waves = (units + slots - 1) / slots;
@@ -645,8 +650,35 @@ BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus, in
         if (ks > cap) ks = cap;
         bl.int_ks = ks;
         bl.int_nch = (L + ks - 1) / ks;
+        bl.int_len = L;
+        if (fit) {
+            // Alternative: one wave of long chunks on the interior's slots,
+            // then one wave of short chunks that start on the closure's CUs
+            // once the closure is done (it takes about kCloseSplits split
+            // times of a bulk workgroup); both waves should end together.
+            const double single = wave_cost((int64_t)tiles * bl.int_nch, ks, slots_int);
+            const int64_t nb64 = slots_int / tiles, ns64 = slots_end / 2 / tiles;
+            const int32_t nb = (int32_t)(nb64 < 32 ? nb64 : 32);
+            const int32_t ns = (int32_t)(ns64 < 32 - nb ? ns64 : 32 - nb);
+            if (nb >= 1 && ns >= 1) {
+                const int32_t xs = (L - nb * kCloseSplits) / (nb + ns) / KC * KC;
+                if (xs >= 2 * KC && xs <= cap) {
+                    const int32_t lb = L - ns * xs;
+                    const int32_t xb = ((lb + nb - 1) / nb + KC - 1) / KC * KC;
+                    const double two = xb + KC > kCloseSplits + xs + KC ? xb + KC
+                                                                         : kCloseSplits + xs + KC;
+                    if (xb <= cap && two < single) {
+                        bl.int_ks = xb;
+                        bl.int_nch = (lb + xb - 1) / xb;
+                        bl.int_len = lb;
+                        bl.int2_ks = xs;
+                        bl.int2_nch = ns;
+                    }
+                }
+            }
+        }
     }
-    bl.PT = bl.int_nch + bl.n_end_ranges * bl.end_nch;
+    bl.PT = bl.int_nch + bl.int2_nch + bl.n_end_ranges * bl.end_nch;
     bl.elems = (size_t)tiles * bl.PT * T * T;
     return bl;
 }
@@ -776,7 +808,10 @@ void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
         const int c = cs.chain, E = cs.D + 1, NT = plan.NT[c];
         if (cs.D < 1 || E < 3 || E >= NT) continue;
         const BulkLayout bl = bulk_layout(NT, E, plan.chains[c].kb, plan.lone, plan.cus, plan.slots_per_cu);
-        add_bulk(inter, cs, E, T, (E - 3) * T + 1, bl.int_ks, bl.int_nch, 0, bl.PT);
+        add_bulk(inter, cs, E, T, bl.int_len, bl.int_ks, bl.int_nch, 0, bl.PT);
+        if (bl.int2_nch)
+            add_bulk(inter, cs, E, T + bl.int_len, (E - 3) * T + 1 - bl.int_len, bl.int2_ks,
+                     bl.int2_nch, bl.int_nch, bl.PT);
     }
     if (inter.nseg) {
         // A short pause on the aux stream lets the closure's workgroups
@@ -795,11 +830,13 @@ void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
         if (cs.D < 1 || E < 2 || E >= NT) continue;
         const BulkLayout bl = bulk_layout(NT, E, plan.chains[c].kb, plan.lone, plan.cus, plan.slots_per_cu);
         if (E == 2) {
-            add_bulk(ends, cs, E, 0, T + 1, bl.end_ks, bl.end_nch, bl.int_nch, bl.PT);
+            add_bulk(ends, cs, E, 0, T + 1, bl.end_ks, bl.end_nch, bl.int_nch + bl.int2_nch,
+                     bl.PT);
         } else {
-            add_bulk(ends, cs, E, 0, T, bl.end_ks, bl.end_nch, bl.int_nch, bl.PT);
-            add_bulk(ends, cs, E, (E - 2) * T + 1, T, bl.end_ks, bl.end_nch,
-                     bl.int_nch + bl.end_nch, bl.PT);
+            const int32_t s0 = bl.int_nch + bl.int2_nch;
+            add_bulk(ends, cs, E, 0, T, bl.end_ks, bl.end_nch, s0, bl.PT);
+            add_bulk(ends, cs, E, (E - 2) * T + 1, T, bl.end_ks, bl.end_nch, s0 + bl.end_nch,
+                     bl.PT);
         }
     }
     if (ends.nseg) push(ends, -1);

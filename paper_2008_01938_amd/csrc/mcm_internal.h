@@ -124,6 +124,8 @@ int bulk_blocks_per_cu();
 // after it.
 struct BulkLayout {
     int32_t int_ks = 0, int_nch = 0;       // interior: splits per chunk, chunks per tile
+    int32_t int_len = 0;                   // ... covering the first int_len interior splits
+    int32_t int2_ks = 0, int2_nch = 0;     // lone: shorter chunks for the rest, launched after
     int32_t end_ks = 0, end_nch = 0;       // each end block: splits per chunk, chunks
     int32_t n_end_ranges = 0;              // 1 (E == 2) or 2
     int32_t PT = 0;                        // partial slots per tile
