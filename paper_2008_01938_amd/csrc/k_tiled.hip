@@ -636,7 +636,7 @@ BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus, in
             // Chunks per tile (at most 32 partial slots) that minimise the
             // estimated duration on the interior's slots.
             double best = 0.0;
-            for (int32_t want = 1; want <= 32 && (want - 1) * KC < L; ++want) {
+            for (int32_t want = 1; want <= kMaxChunks && (want - 1) * KC < L; ++want) {
                 int32_t k = (L + want - 1) / want;
                 k = (k + KC - 1) / KC * KC;
                 const int32_t nch = (L + k - 1) / k;
@@ -658,8 +658,8 @@ BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus, in
             // times of a bulk workgroup); both waves should end together.
             const double single = wave_cost((int64_t)tiles * bl.int_nch, ks, slots_int);
             const int64_t nb64 = slots_int / tiles, ns64 = slots_end / 2 / tiles;
-            const int32_t nb = (int32_t)(nb64 < 32 ? nb64 : 32);
-            const int32_t ns = (int32_t)(ns64 < 32 - nb ? ns64 : 32 - nb);
+            const int32_t nb = (int32_t)(nb64 < kMaxChunks ? nb64 : kMaxChunks);
+            const int32_t ns = (int32_t)(ns64 < kMaxChunks - nb ? ns64 : kMaxChunks - nb);
             if (nb >= 1 && ns >= 1) {
                 const int32_t xs = (L - nb * kCloseSplits) / (nb + ns) / KC * KC;
                 if (xs >= 2 * KC && xs <= cap) {
@@ -681,6 +681,38 @@ BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus, in
     bl.PT = bl.int_nch + bl.int2_nch + bl.n_end_ranges * bl.end_nch;
     bl.elems = (size_t)tiles * bl.PT * T * T;
     return bl;
+}
+
+BulkLayout bulk_layout_chunks(int32_t NT, int32_t E, int32_t kb, int32_t nch)
+{
+    BulkLayout bl = bulk_layout(NT, E, kb, false);
+    if (E < 3 || E >= NT) return bl;
+    const int32_t L = (E - 3) * T + 1;
+    int32_t cap = kb >= 30 ? (1 << 30) : (1 << kb);
+    cap = cap / KC * KC;
+    int32_t most = (L + 63) / 64;
+    if (most > kMaxChunks) most = kMaxChunks;
+    if (nch > most) nch = most;
+    if (nch < 1) nch = 1;
+    int32_t ks = ((L + nch - 1) / nch + KC - 1) / KC * KC;
+    if (ks > cap) ks = cap;
+    bl.int_ks = ks;
+    bl.int_nch = (L + ks - 1) / ks;
+    bl.int_len = L;
+    bl.int2_ks = bl.int2_nch = 0;
+    bl.PT = bl.int_nch + bl.n_end_ranges * bl.end_nch;
+    bl.elems = (size_t)(NT - E) * bl.PT * T * T;
+    return bl;
+}
+
+size_t bulk_part_max(int32_t NT, int32_t kb)
+{
+    size_t most = 0;
+    for (int32_t E = 2; E < NT; ++E) {
+        const size_t e = bulk_layout_chunks(NT, E, kb, kMaxChunks).elems;
+        if (e > most) most = e;
+    }
+    return most;
 }
 
 int bulk_blocks_per_cu()
@@ -754,7 +786,7 @@ void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
         const int c = cs.chain, D = cs.D, NT = plan.NT[c];
         if (D < 1 || D >= NT) continue;
         const int32_t n = plan.chains[c].n;
-        const BulkLayout bl = bulk_layout(NT, D, plan.chains[c].kb, plan.lone, plan.cus, plan.slots_per_cu);
+        const BulkLayout &bl = cs.cur;
         TileSeg sg{};
         sg.part_off = cs.part_cur;
         sg.first = close.blocks;
@@ -807,7 +839,7 @@ void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
     for (const ChainStep &cs : steps) {
         const int c = cs.chain, E = cs.D + 1, NT = plan.NT[c];
         if (cs.D < 1 || E < 3 || E >= NT) continue;
-        const BulkLayout bl = bulk_layout(NT, E, plan.chains[c].kb, plan.lone, plan.cus, plan.slots_per_cu);
+        const BulkLayout &bl = cs.next;
         add_bulk(inter, cs, E, T, bl.int_len, bl.int_ks, bl.int_nch, 0, bl.PT);
         if (bl.int2_nch)
             add_bulk(inter, cs, E, T + bl.int_len, (E - 3) * T + 1 - bl.int_len, bl.int2_ks,
@@ -828,7 +860,7 @@ void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
     for (const ChainStep &cs : steps) {
         const int c = cs.chain, E = cs.D + 1, NT = plan.NT[c];
         if (cs.D < 1 || E < 2 || E >= NT) continue;
-        const BulkLayout bl = bulk_layout(NT, E, plan.chains[c].kb, plan.lone, plan.cus, plan.slots_per_cu);
+        const BulkLayout &bl = cs.next;
         if (E == 2) {
             add_bulk(ends, cs, E, 0, T + 1, bl.end_ks, bl.end_nch, bl.int_nch + bl.int2_nch,
                      bl.PT);
@@ -882,6 +914,10 @@ void plan_lockstep(TiledPlan &plan, const std::vector<int> &ids)
             cs.D = D;
             cs.part_cur = (int64_t)((D & 1) * half) + off_cur[u];
             cs.part_next = (int64_t)(((D + 1) & 1) * half) + off_next[u];
+            cs.cur = bulk_layout(plan.NT[c], D, plan.chains[c].kb, plan.lone, plan.cus,
+                                 plan.slots_per_cu);
+            cs.next = bulk_layout(plan.NT[c], D + 1, plan.chains[c].kb, plan.lone, plan.cus,
+                                  plan.slots_per_cu);
             steps.push_back(cs);
         }
         plan_add_iteration(plan, steps);

@@ -158,19 +158,28 @@ struct TiledPlan {
 };
 
 // One chain's place in an iteration: it advances from tile-diagonal D to
-// D+1.  part_cur: offset of the partial minima of D (read by the closure);
-// part_next: offset of those of D+1 (written by its bulk).
+// D+1.  part_cur: offset of the partial minima of D (read by the closure,
+// laid out as `cur`); part_next: offset of those of D+1 (written by its
+// bulk, laid out as `next`).
 struct ChainStep {
     int chain = 0;
     int D = 0;
     int64_t part_cur = 0;
     int64_t part_next = 0;
+    BulkLayout cur, next;
 };
 
 int32_t tiled_nt(int32_t n);
 // lone: cus / slots_per_cu describe the device (TiledPlan); else ignored.
 BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus = 0,
                        int slots_per_cu = 0);
+// Interior cut into `nch` chunks per tile (clamped to [1, kMaxChunks] and
+// to chunks of at least 64 splits), end blocks in chunks of 64 splits.
+BulkLayout bulk_layout_chunks(int32_t NT, int32_t E, int32_t kb, int32_t nch);
+// Largest partial-minima buffer (uint64) any tile-diagonal of the chain
+// needs under bulk_layout_chunks.
+size_t bulk_part_max(int32_t NT, int32_t kb);
+constexpr int32_t kMaxChunks = 32;
 // Add a chain (offsets as in TileChain); returns its index.
 int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t s_off,
                    int64_t p_off, int64_t pd_off);

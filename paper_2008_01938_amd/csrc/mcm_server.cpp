@@ -91,6 +91,7 @@ struct Request {
     // of part_half uint64 each.
     size_t off = SIZE_MAX, bytes = 0, p_at = 0, pd_at = 0, m_at = 0, s_at = 0, part_at = 0;
     size_t part_half = 0;
+    BulkLayout lay, lay_next;  // bulk layouts of tile-diagonals D and D+1
     int32_t status = MCM_OK;
     double t_submit = 0, t_admit = 0, t_done = 0;
 };
@@ -107,10 +108,7 @@ void layout(Request &r)
     if (r.tiled) {
         int32_t kb = 53 - r.ci.cost_bits;
         if (kb > 20) kb = 20;
-        for (int E = 2; E < r.NT; ++E) {
-            const BulkLayout bl = bulk_layout(r.NT, E, kb, false);
-            if (bl.elems > r.part_half) r.part_half = bl.elems;
-        }
+        r.part_half = bulk_part_max(r.NT, kb);
     }
     r.bytes = r.part_at + align_up(2 * r.part_half * sizeof(uint64_t));
 }
@@ -185,6 +183,18 @@ bool Server::launch_iteration()
             for (size_t t = 0; t < np; ++t) hd[t] = (double)r->p[t];
         });
     }
+    // Interior chunking of this iteration: when the requests' tiles alone do
+    // not fill the device's bulk slots, cut each request's interior into more
+    // chunks, in proportion to its share of the iteration's interior work.
+    const int64_t slots = (int64_t)device_cus() * bulk_blocks_per_cu();
+    double work = 0.0;
+    int64_t tiles_all = 0;
+    for (Request *r : batch) {
+        const int E = r->D + 1;
+        if (!r->tiled || r->D < 1 || E < 3 || E >= r->NT) continue;
+        work += (double)(r->NT - E) * ((E - 3) * 64 + 1);
+        tiles_all += r->NT - E;
+    }
     TiledPlan plan;
     std::vector<ChainStep> steps;
     for (Request *r : batch) {
@@ -198,6 +208,16 @@ bool Server::launch_iteration()
         const int64_t part0 = (int64_t)((r->off + r->part_at) / sizeof(uint64_t));
         cs.part_cur = part0 + (int64_t)((r->D & 1) * r->part_half);
         cs.part_next = part0 + (int64_t)(((r->D + 1) & 1) * r->part_half);
+        const int E = r->D + 1;
+        int32_t nch = 1;
+        if (tiles_all < slots && work > 0.0 && r->D >= 1 && E >= 3 && E < r->NT) {
+            const double tiles = (double)(r->NT - E);
+            const double share = (double)slots * tiles * ((E - 3) * 64 + 1) / work;
+            nch = (int32_t)((share + tiles - 1.0) / tiles);
+        }
+        cs.cur = r->lay;
+        cs.next = bulk_layout_chunks(r->NT, E, plan.chains[cs.chain].kb, nch);
+        r->lay_next = cs.next;
         steps.push_back(cs);
     }
     if (st == MCM_OK && !steps.empty()) {
@@ -229,6 +249,7 @@ bool Server::launch_iteration()
             fin = true;
         } else if (r->tiled) {
             r->D += 1;
+            r->lay = r->lay_next;
             fin = r->D >= r->NT;
         } else {
             fin = true;
@@ -319,6 +340,15 @@ mcm_status mcm_server_create(size_t mem_budget, int32_t max_slots, hipStream_t s
         return MCM_ERR_NO_MEMORY;
     }
     srv->arena = Arena(srv->budget);
+    // Device queries and the library's aux stream are set up here, once, so
+    // that the first iterations do not pay for them.
+    StreamSet warm;
+    if (device_cus() <= 0 || bulk_blocks_per_cu() <= 0 || acquire_streams(0, &warm) != MCM_OK) {
+        (void)hipFree(srv->arena_dev);
+        delete srv;
+        return MCM_ERR_DEVICE;
+    }
+    release_streams(warm);
     srv->stream = stream;
     srv->max_slots = max_slots;
     srv->th = std::thread([srv] { srv->loop(); });
