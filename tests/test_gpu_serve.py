@@ -91,3 +91,25 @@ def test_mixed_paths_and_errors():
             srv.release(99)
         stats = srv.stats()
         assert stats["completed"] == 2 and stats["active"] == 0 and stats["bytes_in_use"] == 0
+
+
+def test_few_large_requests_use_fine_chunks():
+    # Two large requests alone on the server: each iteration cuts their
+    # interiors into many chunks per tile (up to the cap), in proportion to
+    # their work; results must still equal the oracle bit for bit.
+    reqs = {7: workloads.uniform_dims(1800, 1, 1024, 31), 8: workloads.uniform_dims(2600, 1, 1024, 32)}
+    _say("[gpu] serve two large requests (n=1800, n=2600)")
+    got = {}
+    with binding.Server(4 << 30, 4) as srv:
+        for tag, p in reqs.items():
+            srv.submit(p, tag)
+        t_end = binding.clock_now() + 120
+        while len(got) < 2 and binding.clock_now() < t_end:
+            for info in srv.poll():
+                assert info.status == binding.OK
+                got[int(info.tag)] = srv.fetch(info)
+                srv.release(int(info.tag))
+    assert set(got) == set(reqs)
+    for tag, p in reqs.items():
+        om, os_ = oracle.fill(p, threads=oracle.default_threads())
+        assert np.array_equal(got[tag][0], om) and np.array_equal(got[tag][1], os_), f"request {tag}"
