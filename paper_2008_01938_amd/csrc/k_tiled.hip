@@ -210,31 +210,52 @@ __global__ __launch_bounds__(NTH) void k_bulk(const TileChain *__restrict__ chai
         }
     }
 
-    // Staging: A block is T rows x KC columns, B block KC rows x T columns;
-    // 4 elements of each per thread.
+    // Staging: the A block is T rows x KC columns, the B block KC rows x T
+    // columns.  Thread tid stages A rows ar + 16v at split akk and B splits
+    // bkk + 4v at column bc (v = 0..3).  Only the round's base moves, so on
+    // a table under 2 GiB the loads take 32-bit byte offsets from a uniform
+    // base.  In a round that passes kend, splits at or past it are staged
+    // from split kend-1 (inside the table) and masked.
+    static_assert(NTH == 256 && KC == 16 && T == 64, "staging map");
+    const int akk = tid % KC, ar = tid / KC;
+    const int bcol = tid % T, bc = min(bcol, nJ - 1), bkk = tid / T;
+    const bool narrow = (size_t)n * (size_t)n * sizeof(int64_t) < ((size_t)1 << 31);
+    uint32_t oa[4], ob[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        oa[v] = (uint32_t)(((size_t)(row0 + ar + 16 * v) * n + akk) * sizeof(int64_t));
+        ob[v] = (uint32_t)(((size_t)(bkk + 4 * v + 1) * n + col0 + bc) * sizeof(int64_t));
+    }
     int64_t ra[4], rb[4];
     double rp = 0.0;
     auto load = [&](int kc) {
+        if (kc + KC <= kend && narrow) {
+            const char *ba = (const char *)(m + kc);
+            const char *bb = (const char *)(m + (size_t)kc * n);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int e = tid + NTH * v;
-            const int r = e / KC, kk = e % KC;
-            const int k = kc + kk;
-            ra[v] = k < kend ? m[(size_t)(row0 + r) * n + k] : 0;
-            const int kk2 = e / T, c = e % T;
-            const int k2 = kc + kk2;
-            rb[v] = (k2 < kend && c < nJ) ? m[(size_t)(k2 + 1) * n + col0 + c] : 0;
+            for (int v = 0; v < 4; ++v) {
+                ra[v] = *(const int64_t *)(ba + oa[v]);
+                rb[v] = *(const int64_t *)(bb + ob[v]);
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ka = min(kc + akk, kend - 1);
+                ra[v] = m[(size_t)(row0 + ar + 16 * v) * n + ka];
+                const int kb2 = min(kc + bkk + 4 * v, kend - 1);
+                rb[v] = m[(size_t)(kb2 + 1) * n + col0 + bc];
+            }
         }
         if (tid < KC) rp = (kc + tid < kend) ? pd[kc + tid + 1] : 0.0;
     };
     auto store = [&](int kc, int buf) {
+        const bool full = kc + KC <= kend;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int e = tid + NTH * v;
-            const int r = e / KC, kk = e % KC;
-            L.As[buf][kk][r] = (kc + kk < kend) ? (double)ra[v] * scale : kPad;
-            const int kk2 = e / T, c = e % T;
-            L.Bs[buf][kk2][c] = fma((double)rb[v], scale, (double)(kc + kk2 - k0));
+            L.As[buf][akk][ar + 16 * v] =
+                (full || kc + akk < kend) ? (double)ra[v] * scale : kPad;
+            L.Bs[buf][bkk + 4 * v][bcol] =
+                fma((double)rb[v], scale, (double)(kc + bkk + 4 * v - k0));
         }
         if (tid < KC) L.Ps[buf][tid] = rp;
     };
