@@ -43,6 +43,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <type_traits>
 #include <unordered_map>
 
 #include "mcm_internal.h"
@@ -141,11 +142,39 @@ __global__ __launch_bounds__(NTH) void k_tri(const TileChain *__restrict__ chain
 // ------------------------------------------------------------------------
 // Shared memory and launch shapes.
 // ------------------------------------------------------------------------
-constexpr int CG = 16;               // closure: lanes per row group
-constexpr int CTH = T * CG;          // closure: threads (16 waves, 4 per SIMD)
-constexpr int CS = T / CG;           // closure: register slots per lane
-constexpr int CROWS = 64 / CG;       // closure: rows per wave
 constexpr int CSTR = T + 8;          // closure: column stride (doubles) of its LDS tables
+
+// Closure shapes: G lanes per row group, T rows.  G = 16: one tile per CU
+// (16 waves, column-major DJ table).  G = 8: a tile in 8 waves with a packed
+// DJ table, small enough that two closure workgroups share a CU.
+template <int G>
+struct CloseShape {
+    static constexpr int CG = G;          // lanes per row group
+    static constexpr int CTH = T * G;     // threads
+    static constexpr int CS = T / G;      // register slots per lane
+    static constexpr int CROWS = 64 / G;  // rows per wave
+};
+constexpr int CG_LONE = 16;
+constexpr int CG_PAIR = 8;
+
+// Packed DJ table: column c holds DJ[q][c], q = 1..c, from base c; bases
+// step by c plus padding so that consecutive columns start 8 doubles apart
+// modulo 16 (the two row groups of a 16-lane LDS pass then hit disjoint
+// banks).  Reads past a column's length land in later columns or padding:
+// finite values whose terms lose anyway (see close_step).
+constexpr int dj_packed_base(int c)
+{
+    // c(c-1)/2 plus the paddings (8 - x) & 15 for x < c: 120 per 16 columns
+    // and a closed-form prefix for the rest.
+    const int q = c >> 4, rem = c & 15;
+    const int pre = rem <= 9 ? 8 * rem - rem * (rem - 1) / 2
+                             : 36 + 24 * (rem - 9) - ((rem - 1) * rem / 2 - 36);
+    return c * (c - 1) / 2 + 120 * q + pre;
+}
+static_assert(dj_packed_base(1) == 8 && dj_packed_base(9) == 72 && dj_packed_base(16) == 240 &&
+                  dj_packed_base(63) == 2424,
+              "packed DJ bases");
+constexpr int kDJPacked = dj_packed_base(T - 1) + T;
 
 struct BulkLds {
     double As[2][KC][T + 1];  // As[kk][r] = m[row0+r][k] * 2^kb
@@ -153,18 +182,29 @@ struct BulkLds {
     double Ps[2][KC];         // p[k+1]
 };
 
-struct CloseLds {
-    // Column-major with a column stride of CSTR doubles.  LDS has 32 banks
-    // of 4 bytes, so a 64-bit read is conflict-free when the 16 lanes served
-    // together touch distinct 8-byte words modulo 16; in a step those are
-    // the CG = 16 lanes of one row group, reading consecutive rows of one
-    // column.  Row T is a spare so slot addresses never need clamping.
-    double DJt[T][CSTR];  // DJt[c][q] = DJ[q][c] * 2^kb + T + q - 1 (1 <= q <= c), else 0
-    double Xt[T][CSTR];   // Xt[c][q]: bulk key, then final cost * 2^kb of cell (q, c)
+// Closure LDS.  Xt and the full DJ table are column-major with a column
+// stride of CSTR doubles.  LDS has 32 banks of 4 bytes, so a 64-bit read is
+// conflict-free when the 16 lanes served together touch distinct 8-byte
+// words modulo 16: with G = 16 those are one row group reading consecutive
+// rows of one column; with G = 8 two row groups reading adjacent columns,
+// whose starts differ by CSTR = 72 = 8 (mod 16) doubles.  Row T is a spare
+// so slot addresses never need clamping.
+struct CloseLdsFull {
+    double DJt[T][CSTR];   // DJt[c][q] = DJ[q][c] * 2^kb + T + q - 1 (1 <= q <= c), else 0
+    double Xt[T][CSTR];    // Xt[c][q]: bulk key, then final cost * 2^kb of cell (q, c)
     int32_t Ks[T][T + 1];  // bulk split, then final split
     double pJs[T + 1];     // p[col0 + q]
+    __device__ double dj_at(int c, int j) const { return DJt[c][j + 1]; }  // DJ[j+1][c]
+    __device__ double &dj(int q, int c) { return DJt[c][q]; }
 };
-
+struct CloseLdsPacked {
+    double DJp[kDJPacked];  // column c from dj_packed_base(c): DJ[q][c] at q - 1
+    double Xt[T][CSTR];
+    int32_t Ks[T][T + 1];
+    double pJs[T + 1];
+    __device__ double dj_at(int c, int j) const { return DJp[dj_packed_base(c) + j]; }
+    __device__ double &dj(int q, int c) { return DJp[dj_packed_base(c) + q - 1]; }
+};
 
 // ------------------------------------------------------------------------
 // Bulk: workgroup b of a segment takes tile b / nch and chunk b % nch of
@@ -333,32 +373,36 @@ __device__ __forceinline__ double dpp_perm(double v)
     return __builtin_bit_cast(double, o);
 }
 
-// Minimum over each aligned group of 16 lanes (all lanes active).
+// Minimum over each aligned group of G lanes (all lanes active).
+template <int G>
 __device__ __forceinline__ double min_group(double v)
 {
-    v = fmin(v, dpp_perm<0xB1>(v));   // quad_perm [1,0,3,2]: lane ^ 1
-    v = fmin(v, dpp_perm<0x4E>(v));   // quad_perm [2,3,0,1]: lane ^ 2
-    v = fmin(v, dpp_perm<0x141>(v));  // row_half_mirror: i <-> 7-i
-    v = fmin(v, dpp_perm<0x140>(v));  // row_mirror: i <-> 15-i
+    v = fmin(v, dpp_perm<0xB1>(v));                     // quad_perm [1,0,3,2]: lane ^ 1
+    v = fmin(v, dpp_perm<0x4E>(v));                     // quad_perm [2,3,0,1]: lane ^ 2
+    if constexpr (G >= 8) v = fmin(v, dpp_perm<0x141>(v));   // row_half_mirror: i <-> 7-i
+    if constexpr (G >= 16) v = fmin(v, dpp_perm<0x140>(v));  // row_mirror: i <-> 15-i
     return v;
 }
 
+template <int G>
 struct CloseRegs {
-    double DIr[CS], PIr[CS], PJr[CS], Xrow[CS];
+    double DIr[CloseShape<G>::CS], PIr[CloseShape<G>::CS], PJr[CloseShape<G>::CS],
+        Xrow[CloseShape<G>::CS];
 };
 
-template <int T0>  // first (a) slot any row of this wave uses
-__device__ __forceinline__ double close_step(const CloseRegs &R, const double (*Xt)[CSTR],
-                                             const double (*DJt)[CSTR], int cc, int g,
+// One step of a row group: the minimum over its (a) and (b) splits of cell
+// (r, cc).  Every (b) slot is read: a slot whose cell is not final yet still
+// holds Xrow = 2^62, so whatever DJ value it meets, its term loses.
+template <int G, int T0, class Lds>  // T0: first (a) slot any row of this wave uses
+__device__ __forceinline__ double close_step(const CloseRegs<G> &R, const Lds &L, int cc, int g,
                                              double pJc)
 {
+    constexpr int CS = CloseShape<G>::CS;
     double xa[CS], xb[CS];
 #pragma unroll
-    for (int t = T0; t < CS; ++t) xa[t] = Xt[cc][t * CG + g + 1];
-    // All (b) slots are read: DJt is zero outside its triangle, and a slot
-    // whose cell is not final yet still holds Xrow = 2^62.
+    for (int t = T0; t < CS; ++t) xa[t] = L.Xt[cc][t * G + g + 1];
 #pragma unroll
-    for (int t = 0; t < CS; ++t) xb[t] = DJt[cc][t * CG + g + 1];
+    for (int t = 0; t < CS; ++t) xb[t] = L.dj_at(cc, t * G + g);
     // Independent terms, then a balanced min tree.
     double v[CS];
 #pragma unroll
@@ -370,17 +414,30 @@ __device__ __forceinline__ double close_step(const CloseRegs &R, const double (*
     for (int span = 1; span < CS; span *= 2)
 #pragma unroll
         for (int t = 0; t + span < CS; t += 2 * span) v[t] = fmin(v[t], v[t + span]);
-    return min_group(v[0]);
+    return min_group<G>(v[0]);
 }
 
-__global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ chains,
-                                               const TileSeg *__restrict__ segs, int nseg,
-                                               int64_t *__restrict__ m_all,
-                                               int32_t *__restrict__ s_all,
-                                               const double *__restrict__ pd_all,
-                                               const uint64_t *__restrict__ part_all)
+// close_step with its first (a) slot t0 (wave-uniform) as a template argument.
+template <int G, int T0, class Lds>
+__device__ __forceinline__ double close_step_at(int t0, const CloseRegs<G> &R, const Lds &L,
+                                                int cc, int g, double pJc)
 {
-    __shared__ CloseLds L;
+    if constexpr (T0 + 1 < CloseShape<G>::CS) {
+        if (t0 > T0) return close_step_at<G, T0 + 1>(t0, R, L, cc, g, pJc);
+    }
+    return close_step<G, T0>(R, L, cc, g, pJc);
+}
+
+template <int G, class Lds>
+__device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__ chains,
+                                           const TileSeg *__restrict__ segs, int nseg,
+                                           int64_t *__restrict__ m_all,
+                                           int32_t *__restrict__ s_all,
+                                           const double *__restrict__ pd_all,
+                                           const uint64_t *__restrict__ part_all)
+{
+    constexpr int CTH = CloseShape<G>::CTH, CS = CloseShape<G>::CS;
+    constexpr int CROWS = CloseShape<G>::CROWS;
     const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
     const TileChain ch = chains[sg.chain];
     const int local = blockIdx.x - sg.first;
@@ -397,13 +454,13 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
     const double inv_scale = ldexp(1.0, -kb);
     const uint64_t kmask = (((uint64_t)1) << kbits) - 1;
 
-    const int r = tid / CG, g = tid % CG;
+    const int r = tid / G, g = tid % G;
     const int h = __builtin_amdgcn_readfirstlane(tid / 64);  // rows CROWS*h ..
-    CloseRegs R;
+    CloseRegs<G> R;
     const double pi_s = pd[row0 + r] * scale;
 #pragma unroll
     for (int t = 0; t < CS; ++t) {
-        const int q = t * CG + g;  // (a) split column q; (b) split column c' = q
+        const int q = t * G + g;  // (a) split column q; (b) split column c' = q
         const bool qa = q >= r && q <= T - 2;
         R.DIr[t] = qa ? fma((double)m[(size_t)(row0 + r) * n + row0 + q], scale, (double)q) : kPad;
         R.PIr[t] = qa ? pi_s * pd[row0 + q + 1] : 0.0;
@@ -412,9 +469,16 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
     }
 
     for (int q = tid; q <= T; q += CTH) L.pJs[q] = q <= nJ ? pd[col0 + q] : 0.0;
-    for (int idx = tid; idx < T * CSTR; idx += CTH) {
-        (&L.DJt[0][0])[idx] = 0.0;
-        (&L.Xt[0][0])[idx] = 0.0;
+    {
+        double *z = &L.Xt[0][0];
+        for (int idx = tid; idx < T * CSTR; idx += CTH) z[idx] = 0.0;
+        if constexpr (std::is_same<Lds, CloseLdsFull>::value) {
+            double *zd = &L.dj(0, 0);
+            for (int idx = tid; idx < T * CSTR; idx += CTH) zd[idx] = 0.0;
+        } else {
+            double *zd = &L.dj(1, 0);
+            for (int idx = tid; idx < kDJPacked; idx += CTH) zd[idx] = 0.0;
+        }
     }
     __syncthreads();
     // DJ[q][c], 1 <= q <= c < nJ, read row-major (coalesced).
@@ -422,8 +486,8 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
     for (int idx = tid; idx < T * T; idx += CTH) {
         const int qq = idx / T, c = idx % T;
         if (qq >= 1 && qq <= c && c < nJ)
-            L.DJt[c][qq] = fma((double)m[(size_t)(col0 + qq) * n + col0 + c], scale,
-                               (double)(T + qq - 1));
+            L.dj(qq, c) = fma((double)m[(size_t)(col0 + qq) * n + col0 + c], scale,
+                              (double)(T + qq - 1));
     }
     // Bulk result per cell: the minimum of the PT packed (cost << kbits | k)
     // partials, or for D == 1 the single bulk split k = (I+1)T-1 whose
@@ -438,7 +502,7 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
         for (int u = 0; u < CPT; ++u) {
             const int idx = tid + CTH * u;
             const int rr = idx / T, c = idx % T;
-            if (idx < T * T && c < nJ) {
+            if (c < nJ) {
                 const int64_t cost = m[(size_t)(row0 + rr) * n + k] +
                                      m[(size_t)(k + 1) * n + col0 + c] +
                                      (int64_t)pd[row0 + rr] * (int64_t)pd[k + 1] *
@@ -454,8 +518,8 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
 #pragma unroll
             for (int u = 0; u < CPT; ++u) {
                 const int idx = tid + CTH * u;
-                v0[u] = idx < T * T ? src[(size_t)sl * T * T + idx] : UINT64_MAX;
-                v1[u] = idx < T * T ? src[(size_t)(sl + 1) * T * T + idx] : UINT64_MAX;
+                v0[u] = src[(size_t)sl * T * T + idx];
+                v1[u] = src[(size_t)(sl + 1) * T * T + idx];
             }
 #pragma unroll
             for (int u = 0; u < CPT; ++u) {
@@ -466,8 +530,7 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
         if (sl < PT) {
 #pragma unroll
             for (int u = 0; u < CPT; ++u) {
-                const int idx = tid + CTH * u;
-                const uint64_t w = idx < T * T ? src[(size_t)sl * T * T + idx] : UINT64_MAX;
+                const uint64_t w = src[(size_t)sl * T * T + tid + CTH * u];
                 key[u] = w < key[u] ? w : key[u];
             }
         }
@@ -476,15 +539,14 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
     for (int u = 0; u < CPT; ++u) {
         const int idx = tid + CTH * u;
         const int rr = idx / T, c = idx % T;
-        if (idx < T * T && c < nJ) {
+        if (c < nJ) {
             L.Xt[c][rr] = fma((double)(int64_t)(key[u] >> kbits), scale, (double)(T - 1));
             L.Ks[rr][c] = (int32_t)(key[u] & kmask);
         }
     }
     __syncthreads();
 
-    // The sweep is the critical path of the solve; bulk workgroups sharing
-    // the CU fill the issue slots it leaves idle.
+    // The sweep is the critical path of the solve.
     __builtin_amdgcn_s_setprio(3);
     const int wmax = (T - 1) + (nJ - 1);
     for (int w = 0; w <= wmax; ++w) {
@@ -495,20 +557,14 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
             const int cc = min(max(c, 0), nJ - 1);
             const double pJc = L.pJs[cc + 1];
             const double xbulk = L.Xt[cc][r];
-            double best;
-            switch ((h * CROWS) / CG) {  // wave-uniform first (a) slot
-            case 0: best = close_step<0>(R, L.Xt, L.DJt, cc, g, pJc); break;
-            case 1: best = close_step<1>(R, L.Xt, L.DJt, cc, g, pJc); break;
-            case 2: best = close_step<2>(R, L.Xt, L.DJt, cc, g, pJc); break;
-            default: best = close_step<3>(R, L.Xt, L.DJt, cc, g, pJc); break;
-            }
+            const double best = close_step_at<G, 0>((h * CROWS) / G, R, L, cc, g, pJc);
             const double fin = fmin(best, xbulk);
             const double cost = floor(fin * inv_scale);
             const double xv = cost * scale;
             if (c >= 0 && c < nJ) {
 #pragma unroll
                 for (int t = 0; t < CS; ++t)
-                    if (t * CG + g == c) R.Xrow[t] = xv;
+                    if (t * G + g == c) R.Xrow[t] = xv;
                 if (g == 0) {
                     L.Xt[c][r] = xv;
                     const int kl = (int)fma(-cost, scale, fin);
@@ -537,14 +593,34 @@ __global__ __launch_bounds__(CTH) void k_close(const TileChain *__restrict__ cha
     }
 }
 
-static_assert(CG == 16 && CS == 4 && CROWS == 4, "close_step dispatch assumes 4 slots");
+// One tile per CU (lone chains: the closure is their critical path).
+__global__ __launch_bounds__(CloseShape<CG_LONE>::CTH) void k_close(
+    const TileChain *__restrict__ chains, const TileSeg *__restrict__ segs, int nseg,
+    int64_t *__restrict__ m_all, int32_t *__restrict__ s_all, const double *__restrict__ pd_all,
+    const uint64_t *__restrict__ part_all)
+{
+    __shared__ CloseLdsFull L;
+    close_tile<CG_LONE>(L, chains, segs, nseg, m_all, s_all, pd_all, part_all);
+}
 
-// Dynamic LDS requested on top of CloseLds by every closure launch, so that
-// no bulk workgroup fits beside a closure workgroup on a CU (160 KB per CU):
-// the closure's sweep is latency-bound and slows down several-fold next to
-// a bulk workgroup.
-constexpr size_t kCloseExtraLds = 163840 - sizeof(CloseLds) - sizeof(BulkLds) + 1024;
-static_assert(sizeof(CloseLds) + kCloseExtraLds <= 163840, "closure LDS exceeds a CU");
+// Two tiles per CU (many chains: closure throughput matters).
+__global__ __launch_bounds__(CloseShape<CG_PAIR>::CTH) void k_close_pair(
+    const TileChain *__restrict__ chains, const TileSeg *__restrict__ segs, int nseg,
+    int64_t *__restrict__ m_all, int32_t *__restrict__ s_all, const double *__restrict__ pd_all,
+    const uint64_t *__restrict__ part_all)
+{
+    __shared__ CloseLdsPacked L;
+    close_tile<CG_PAIR>(L, chains, segs, nseg, m_all, s_all, pd_all, part_all);
+}
+
+static_assert(2 * sizeof(CloseLdsPacked) <= 163840, "two paired closures per CU");
+
+// Dynamic LDS requested on top of CloseLdsFull by every lone closure launch,
+// so that no bulk workgroup fits beside it on a CU (160 KB per CU): the
+// sweep is latency-bound and slows down several-fold next to a bulk
+// workgroup.
+constexpr size_t kCloseExtraLds = 163840 - sizeof(CloseLdsFull) - sizeof(BulkLds) + 1024;
+static_assert(sizeof(CloseLdsFull) + kCloseExtraLds <= 163840, "closure LDS exceeds a CU");
 
 // A bounded pause (constant-rate wall clock) on the stream it runs on.
 __global__ __launch_bounds__(64) void k_delay(long long ticks)
@@ -989,6 +1065,7 @@ mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double 
         forked = st == MCM_OK;
     }
     const long long delay_ticks = aux ? delay_ticks_for_device() : 0;
+    const int cus = device_cus();
     for (size_t li = 0; li < plan.launches.size() && st == MCM_OK; ++li) {
         const TiledLaunch &L = plan.launches[li];
         hipStream_t q = L.stream == 1 ? ss.aux : stream;
@@ -1012,8 +1089,14 @@ mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double 
             e = hipGetLastError();
         } else if (L.kind == TK_CLOSE) {
             ProfileScope ps(KC_CLOSE, q, L.evals);
-            hipLaunchKernelGGL(k_close, dim3(L.blocks), dim3(CTH), kCloseExtraLds, q, chains, sg,
-                               L.nseg, m_all, s_all, pd, part);
+            // Paired closures (two per CU, each somewhat slower) only when
+            // the launch has more tiles than the device has CUs.
+            if (plan.lone || L.blocks <= cus)
+                hipLaunchKernelGGL(k_close, dim3(L.blocks), dim3(CloseShape<CG_LONE>::CTH),
+                                   kCloseExtraLds, q, chains, sg, L.nseg, m_all, s_all, pd, part);
+            else
+                hipLaunchKernelGGL(k_close_pair, dim3(L.blocks), dim3(CloseShape<CG_PAIR>::CTH),
+                                   0, q, chains, sg, L.nseg, m_all, s_all, pd, part);
             e = hipGetLastError();
         } else {
             hipLaunchKernelGGL(k_delay, dim3(1), dim3(64), 0, q, delay_ticks);
