@@ -979,42 +979,49 @@ void plan_lockstep(TiledPlan &plan, const std::vector<int> &ids)
     // so positional offsets agree between writer and reader.
     int maxNT = 0;
     for (int c : ids) maxNT = plan.NT[c] > maxNT ? plan.NT[c] : maxNT;
-    auto offsets = [&](int E, std::vector<int64_t> &off) {
-        size_t used = 0;
-        off.assign(ids.size(), 0);
-        for (size_t u = 0; u < ids.size(); ++u) {
-            const int c = ids[u];
-            const BulkLayout bl = bulk_layout(plan.NT[c], E, plan.chains[c].kb, plan.lone, plan.cus,
-                                                plan.slots_per_cu);
-            off[u] = (int64_t)used;
-            used += bl.elems;
+    // Layouts depend on (NT, kb) only: compute each once (many chains of a
+    // batch share them).
+    std::unordered_map<int64_t, std::vector<BulkLayout>> cache;
+    auto layouts = [&](int c) -> const std::vector<BulkLayout> & {
+        const int NT = plan.NT[c], kb = plan.chains[c].kb;
+        std::vector<BulkLayout> &v = cache[(int64_t)NT * 64 + kb];
+        if (v.empty()) {
+            v.resize((size_t)NT + 1);
+            for (int E = 0; E <= NT; ++E)
+                v[E] = bulk_layout(NT, E, kb, plan.lone, plan.cus, plan.slots_per_cu);
         }
-        return used;
+        return v;
     };
-    std::vector<int64_t> off;
+    std::vector<const std::vector<BulkLayout> *> lay(ids.size());
+    for (size_t u = 0; u < ids.size(); ++u) lay[u] = &layouts(ids[u]);
+    auto elems = [&](size_t u, int E) {
+        return E < (int)lay[u]->size() ? (*lay[u])[E].elems : (size_t)0;
+    };
     size_t half = 0;
     for (int E = 2; E < maxNT; ++E) {
-        const size_t used = offsets(E, off);
+        size_t used = 0;
+        for (size_t u = 0; u < ids.size(); ++u) used += elems(u, E);
         if (used > half) half = used;
     }
     plan.part_elems = 2 * half;
-    std::vector<int64_t> off_cur, off_next;
+    std::vector<ChainStep> steps;
+    steps.reserve(ids.size());
     for (int D = 0; D < maxNT; ++D) {
-        offsets(D, off_cur);
-        offsets(D + 1, off_next);
-        std::vector<ChainStep> steps;
+        size_t used_cur = 0, used_next = 0;
+        steps.clear();
         for (size_t u = 0; u < ids.size(); ++u) {
             const int c = ids[u];
+            const size_t oc = used_cur, on = used_next;
+            used_cur += elems(u, D);
+            used_next += elems(u, D + 1);
             if (D >= plan.NT[c]) continue;
             ChainStep cs;
             cs.chain = c;
             cs.D = D;
-            cs.part_cur = (int64_t)((D & 1) * half) + off_cur[u];
-            cs.part_next = (int64_t)(((D + 1) & 1) * half) + off_next[u];
-            cs.cur = bulk_layout(plan.NT[c], D, plan.chains[c].kb, plan.lone, plan.cus,
-                                 plan.slots_per_cu);
-            cs.next = bulk_layout(plan.NT[c], D + 1, plan.chains[c].kb, plan.lone, plan.cus,
-                                  plan.slots_per_cu);
+            cs.part_cur = (int64_t)((D & 1) * half + oc);
+            cs.part_next = (int64_t)(((D + 1) & 1) * half + on);
+            cs.cur = (*lay[u])[D];
+            cs.next = (*lay[u])[D + 1];
             steps.push_back(cs);
         }
         plan_add_iteration(plan, steps);

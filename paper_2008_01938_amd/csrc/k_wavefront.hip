@@ -21,6 +21,15 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// pd[t] = p[t]: exact fp64 copies of dimensions (grid-stride).
+__global__ __launch_bounds__(kBlock) void k_widen(const int32_t *__restrict__ p,
+                                                  double *__restrict__ pd, size_t count)
+{
+    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < count;
+         t += (size_t)gridDim.x * kBlock)
+        pd[t] = (double)p[t];
+}
+
 __device__ __forceinline__ void lex_min(int64_t &v, int32_t &k, int64_t v2, int32_t k2)
 {
     if (v2 < v || (v2 == v && k2 < k)) {
@@ -94,6 +103,15 @@ hipError_t launch_diag(const int32_t *p, int32_t n, int32_t d, int64_t *m, int32
 }
 
 }  // namespace
+
+mcm_status widen_dims(const int32_t *p, double *pd, size_t count, hipStream_t stream)
+{
+    if (count == 0) return MCM_OK;
+    size_t blocks = (count + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_widen, dim3((unsigned)blocks), dim3(kBlock), 0, stream, p, pd, count);
+    return hipGetLastError() == hipSuccess ? MCM_OK : MCM_ERR_DEVICE;
+}
 
 mcm_status run_wavefront(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int32_t *s,
                          hipStream_t stream)

@@ -20,11 +20,12 @@ namespace mcm {
 mcm_status check_chain(const int32_t *p, int32_t n, ChainInfo *ci)
 {
     if (p == nullptr || n < 1) return MCM_ERR_INVALID_ARG;
-    int32_t pmax = 0;
-    for (int32_t t = 0; t <= n; ++t) {
-        if (p[t] < 1) return MCM_ERR_INVALID_ARG;
-        if (p[t] > pmax) pmax = p[t];
+    int32_t pmin = INT32_MAX, pmax = 0;
+    for (int32_t t = 0; t <= n; ++t) {  // branch-free, so it vectorises
+        pmin = p[t] < pmin ? p[t] : pmin;
+        pmax = p[t] > pmax ? p[t] : pmax;
     }
+    if (pmin < 1) return MCM_ERR_INVALID_ARG;
     unsigned __int128 bound = (unsigned __int128)(uint64_t)pmax * (uint64_t)pmax;
     bound *= (uint64_t)pmax;
     bound *= (uint64_t)(n - 1);
@@ -413,18 +414,28 @@ mcm_status mcm_solve_batched(int32_t count, const int32_t *n, const int64_t *p_o
     }
     if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
 
-    // All dims in one upload: p_len int32 (padded to 8 bytes), then p_len doubles.
+    // All dims in one upload of p_len int32 (padded to 8 bytes); their fp64
+    // copies are made on the device, after it.
     const size_t np = (size_t)p_len;
     const size_t off_d = (np * sizeof(int32_t) + 7) / 8 * 8;
     void *dev = nullptr;
-    mcm_status st = upload_blob(stream, &dev, off_d + np * sizeof(double), [&](char *h) {
+    mcm_status st = upload_blob(stream, &dev, off_d, [&](char *h) {
         memcpy(h, p_all, np * sizeof(int32_t));
-        double *hd = (double *)(h + off_d);
-        for (size_t t = 0; t < np; ++t) hd[t] = (double)p_all[t];
     });
     if (st != MCM_OK) return st;
+    double *pd_own = nullptr;
+    if (ws_alloc((void **)&pd_own, np * sizeof(double), stream) != hipSuccess) {
+        ws_free(dev, stream);
+        return MCM_ERR_NO_MEMORY;
+    }
     const int32_t *p_dev = (const int32_t *)dev;
-    const double *pd_dev = (const double *)((char *)dev + off_d);
+    const double *pd_dev = pd_own;
+    st = widen_dims(p_dev, pd_own, np, stream);
+    if (st != MCM_OK) {
+        ws_free(pd_own, stream);
+        ws_free(dev, stream);
+        return st;
+    }
 
     TiledPlan plan;
     std::vector<int> ids;
@@ -445,6 +456,7 @@ mcm_status mcm_solve_batched(int32_t count, const int32_t *n, const int64_t *p_o
         dc.pd = pd_dev + p_off[b];
         st = run_wavefront(dc, ci[b], m_all + tab_off[b], s_all + tab_off[b], stream);
     }
+    ws_free(pd_own, stream);
     ws_free(dev, stream);
     return st;
 }

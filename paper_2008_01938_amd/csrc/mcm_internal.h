@@ -132,6 +132,9 @@ struct BulkLayout {
     size_t elems = 0;                      // partial-minima elements (uint64) of all tiles
 };
 
+// pd[t] = p[t] for t < count, on the device.
+mcm_status widen_dims(const int32_t *p, double *pd, size_t count, hipStream_t stream);
+
 // Wavefront path (int64, any valid input).
 mcm_status run_wavefront(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int32_t *s,
                          hipStream_t stream);
