@@ -710,7 +710,7 @@ BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus, in
     // End blocks: E == 2 has a single range of T+1 splits, E >= 3 two of T.
     const int32_t end_len = E == 2 ? T + 1 : T;
     bl.n_end_ranges = E == 2 ? 1 : 2;
-    int32_t end_ks = 64;
+    int32_t end_ks = (end_len + KC - 1) / KC * KC;  // one chunk per range
     if (fit) {
         double best = 0.0;
         for (int32_t ks = KC; ks <= end_len + KC - 1; ks += KC) {
