@@ -150,11 +150,20 @@ def bench_serving(binding, workloads, torch, count: int, rate: float):
     st = workloads.serving_stream(count=count, rate=rate, seed=4)
     served = serve.run_served(st, mem_budget=24 << 30, max_slots=256).summary()
     plain = serve.run_plain(st).summary()
+    # Saturation: the same requests all arriving at once; throughput is
+    # requests over the time to finish them all.
+    sat = workloads.serving_stream(count=count, rate=1e12, seed=4)
+    sat_served = serve.run_served(sat, mem_budget=24 << 30, max_slots=256).summary()
+    sat_plain = serve.run_plain(sat).summary()
     return {"workload": f"mcm_serving (first {count} requests of the seed-4 stream, "
                         f"Poisson {rate:g}/s, n log-uniform [8,4096], dims [1,1024])",
             "served": served, "plain": plain,
             "p99_speedup_vs_plain": plain["p99_ms"] / served["p99_ms"],
-            "p50_speedup_vs_plain": plain["p50_ms"] / served["p50_ms"]}
+            "p50_speedup_vs_plain": plain["p50_ms"] / served["p50_ms"],
+            "saturation": {"served_requests_per_s": sat_served["requests_per_s"],
+                           "plain_requests_per_s": sat_plain["requests_per_s"],
+                           "speedup_vs_plain": sat_served["requests_per_s"] /
+                           sat_plain["requests_per_s"]}}
 
 
 def traffic_probe(binding, torch, chain, m, s):
