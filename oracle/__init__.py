@@ -15,6 +15,8 @@ Two independent implementations live here:
 * :mod:`oracle.linear`: the paper's own formulation -- the triangular table
   linearised into a 1-D array ``ST`` in diagonal order and every element
   computed by Eq. (2) from its operand pairs -- in pure Python, for small n.
+* :mod:`oracle.paren`: the optimal product order read back from a split
+  table by the textbook recursion (tree, cost and parenthesized text).
 
 Neither is trusted on its own: ``tests/test_oracle.py`` pins both against
 brute-force enumeration of parenthesizations, closed forms, invariants and
