@@ -162,6 +162,62 @@ int32_t mcm_chain_n(const mcm_chain *chain);
 void mcm_chain_destroy(mcm_chain *chain, hipStream_t stream);
 
 /*
+ * Optimal order read back from a split table.  Section IV of the paper
+ * takes the MCM problem from the textbook formulation it cites, where the
+ * optimal product order follows from s by recursion: matrices i..j are
+ * multiplied as (i..s[i][j]) times (s[i][j]+1..j).  The n-1 products of the
+ * tree are named by their split k (the product that joins matrix k to
+ * matrix k+1); for each, the call reports the matrices it spans.
+ *
+ *   mcm_parens_length  characters of the parenthesized text of n matrices
+ *                      (any order has the same length): 2(n-1) for the
+ *                      parentheses plus, per matrix t, "A" and the decimal
+ *                      digits of t.  -1 for n < 1.  Host only.
+ *
+ *   mcm_parenthesize   one chain.
+ *     p      host, n+1 dims (read before return); required when cost is
+ *            given (validated as in mcm_check_chain), else may be NULL.
+ *     n      number of matrices, >= 1.
+ *     s      device, n*n int32 split table, row-major, as written by
+ *            mcm_solve (only s[i][j], i < j, on the tree's cells is read).
+ *     lo, hi device, n-1 int32 each, 4-byte aligned, or both NULL: product
+ *            k multiplies (A_lo[k] .. A_k) by (A_k+1 .. A_hi[k]).
+ *     cost   device, one int64, or NULL: the scalar multiplications of the
+ *            tree, sum over k of p[lo[k]] * p[k+1] * p[hi[k]+1]; equal to
+ *            m[0][n-1] when s is the table mcm_solve wrote for p.
+ *     text   device, mcm_parens_length(n)+1 bytes, or NULL: the fully
+ *            parenthesized product, matrices written A0, A1, ... (0-based),
+ *            e.g. "((A0A1)A2)", NUL-terminated; "A0" for n = 1.
+ *   A table entry on the tree's path that is not a split of its cell
+ *   (s[i][j] outside [i, j-1]) is not followed: lo/hi of the products below
+ *   it stay -1, cost is -1 and text is the empty string.  Work is enqueued
+ *   on `stream` like mcm_solve; workspace is stream-ordered.
+ *
+ *   mcm_parenthesize_batched  many chains, one workgroup each, one launch.
+ *     count     chains (>= 0; 0 is a no-op).
+ *     n         host, count entries (>= 1).
+ *     tab_off   host: chain b's split table is s_all + tab_off[b] (n*n).
+ *     node_off  host: chain b's products are lo_all/hi_all + node_off[b]
+ *               (n[b]-1 entries each; ranges of different chains must not
+ *               overlap).
+ *     cost_all  device, count int64, or NULL: per-chain tree cost, needing
+ *               p_off/p_all (host, as in mcm_solve_batched).
+ *   Same invalid-table behaviour per chain.  All chains are validated
+ *   before anything is enqueued.
+ * Errors: MCM_ERR_INVALID_ARG (bad sizes, offsets, alignment, one of lo/hi
+ * NULL, cost without p), MCM_ERR_OVERFLOW (from validating p),
+ * MCM_ERR_NO_MEMORY, MCM_ERR_DEVICE.
+ */
+int64_t mcm_parens_length(int32_t n);
+mcm_status mcm_parenthesize(const int32_t *p, int32_t n, const int32_t *s, int32_t *lo,
+                            int32_t *hi, int64_t *cost, char *text, hipStream_t stream);
+mcm_status mcm_parenthesize_batched(int32_t count, const int32_t *n, const int64_t *p_off,
+                                    const int32_t *p_all, const int64_t *tab_off,
+                                    const int32_t *s_all, const int64_t *node_off,
+                                    int32_t *lo_all, int32_t *hi_all, int64_t *cost_all,
+                                    hipStream_t stream);
+
+/*
  * Request server: continuous batching of many chains on one device.
  *
  * The server owns one device arena of `mem_budget` bytes from which each

@@ -35,7 +35,8 @@ EXPORTED = (
     "mcm_solve", "mcm_solve_algo", "mcm_solve_batched", "mcm_chain_create", "mcm_chain_solve", "mcm_chain_n",
     "mcm_chain_destroy", "mcm_server_create", "mcm_server_submit", "mcm_server_poll",
     "mcm_server_release", "mcm_server_request_bytes", "mcm_server_stats", "mcm_server_destroy", "mcm_clock_now",
-    "mcm_profile_enable", "mcm_profile_read",
+    "mcm_profile_enable", "mcm_profile_read", "mcm_parens_length", "mcm_parenthesize",
+    "mcm_parenthesize_batched",
 )
 
 
@@ -121,6 +122,13 @@ def load() -> ctypes.CDLL:
                                              ctypes.POINTER(ctypes.c_int64),
                                              ctypes.POINTER(ctypes.c_double)]
             lib.mcm_profile_read.restype = ctypes.c_int
+            lib.mcm_parens_length.argtypes = [ctypes.c_int32]
+            lib.mcm_parens_length.restype = ctypes.c_int64
+            lib.mcm_parenthesize.argtypes = [i32p, ctypes.c_int32, vp, vp, vp, vp, vp, vp]
+            lib.mcm_parenthesize.restype = ctypes.c_int
+            lib.mcm_parenthesize_batched.argtypes = [ctypes.c_int32, i32p, i64p, i32p, i64p, vp,
+                                                     i64p, vp, vp, vp, vp]
+            lib.mcm_parenthesize_batched.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -230,6 +238,115 @@ def solve_batched_into(ns, p_off, p_all, tab_off, m_all, s_all, stream=None) -> 
                                   ctypes.c_void_p(_stream_handle(stream)))
     if st != OK:
         raise MCMError(st, "mcm_solve_batched")
+
+
+def parens_length(n: int) -> int:
+    """mcm_parens_length: characters of the parenthesized text of n matrices."""
+    return int(load().mcm_parens_length(int(n)))
+
+
+def _ptr_or_null(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def parenthesize_into(s, n: int, p=None, lo=None, hi=None, cost=None, text=None,
+                      stream=None) -> None:
+    """Enqueue mcm_parenthesize for the n x n split table s (CUDA int32).
+
+    lo, hi: CUDA int32 tensors of n-1 elements (or both None); cost: CUDA
+    int64 tensor of one element (needs p); text: CUDA uint8 tensor of
+    parens_length(n)+1 bytes.  Any output may be None.
+    """
+    import torch
+    if not (s.is_cuda and s.dtype == torch.int32 and s.is_contiguous() and s.numel() >= n * n):
+        raise TypeError("s must be a contiguous CUDA int32 tensor of n*n elements")
+    for t, dt, need in ((lo, torch.int32, n - 1), (hi, torch.int32, n - 1),
+                        (cost, torch.int64, 1), (text, torch.uint8, parens_length(n) + 1)):
+        if t is not None and not (t.is_cuda and t.dtype == dt and t.is_contiguous() and
+                                  t.numel() >= need):
+            raise TypeError("output tensor of the wrong type or size")
+    a = _dims(p) if p is not None else None
+    if a is not None and a.size != n + 1:
+        raise ValueError("p must have n+1 entries")
+    st = load().mcm_parenthesize(_p_ptr(a) if a is not None else None, int(n),
+                                 ctypes.c_void_p(s.data_ptr()), _ptr_or_null(lo),
+                                 _ptr_or_null(hi), _ptr_or_null(cost), _ptr_or_null(text),
+                                 ctypes.c_void_p(_stream_handle(stream)))
+    if st != OK:
+        raise MCMError(st, "mcm_parenthesize")
+
+
+def parenthesize(s, p=None, stream=None):
+    """Tree of the split table s (n x n CUDA int32) on the device.
+
+    Returns (lo, hi, cost, text): lo/hi CUDA int32 tensors (n-1), cost an
+    int (None without p), text a str.  Synchronises the stream to read
+    cost and text.
+    """
+    import torch
+    n = int(s.shape[0])
+    dev = s.device
+    lo = torch.empty(max(n - 1, 0), dtype=torch.int32, device=dev)
+    hi = torch.empty(max(n - 1, 0), dtype=torch.int32, device=dev)
+    cost = torch.empty(1, dtype=torch.int64, device=dev) if p is not None else None
+    text = torch.empty(parens_length(n) + 1, dtype=torch.uint8, device=dev)
+    parenthesize_into(s, n, p=p, lo=lo if n > 1 else None, hi=hi if n > 1 else None,
+                      cost=cost, text=text, stream=stream)
+    raw = text.cpu().numpy().tobytes()
+    return (lo, hi, int(cost.item()) if cost is not None else None,
+            raw[:raw.index(b"\0")].decode("ascii"))
+
+
+def parenthesize_batched_into(ns, tab_off, s_all, node_off, lo_all, hi_all, p_off=None,
+                              p_all=None, cost_all=None, stream=None) -> None:
+    """Enqueue mcm_parenthesize_batched (offsets as in solve_batched_into;
+    chain b's products at node_off[b] of lo_all / hi_all)."""
+    import torch
+    ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
+    tab_off = np.ascontiguousarray(np.asarray(tab_off, dtype=np.int64))
+    node_off = np.ascontiguousarray(np.asarray(node_off, dtype=np.int64))
+    count = ns.size
+    if not (tab_off.size == count and node_off.size == count):
+        raise ValueError("ns, tab_off and node_off must have one entry per chain")
+    for t, dt in ((s_all, torch.int32), (lo_all, torch.int32), (hi_all, torch.int32)):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+            raise TypeError("s_all / lo_all / hi_all must be contiguous CUDA int32 tensors")
+    if count:
+        if np.any(ns < 1) or np.any(tab_off < 0) or np.any(node_off < 0):
+            raise ValueError("n >= 1 and non-negative offsets required")
+        if int(np.max(tab_off + ns.astype(np.int64) ** 2)) > s_all.numel():
+            raise ValueError("s_all too small for the given table offsets")
+        if int(np.max(node_off + ns - 1)) > min(lo_all.numel(), hi_all.numel()):
+            raise ValueError("lo_all / hi_all too small for the given node offsets")
+    i64 = ctypes.POINTER(ctypes.c_int64)
+    pa = po = None
+    if cost_all is not None:
+        if p_off is None or p_all is None:
+            raise ValueError("cost_all needs p_off and p_all")
+        if not (cost_all.is_cuda and cost_all.dtype == torch.int64 and
+                cost_all.is_contiguous() and cost_all.numel() >= count):
+            raise TypeError("cost_all must be a contiguous CUDA int64 tensor of count entries")
+        po = np.ascontiguousarray(np.asarray(p_off, dtype=np.int64))
+        pa = np.ascontiguousarray(np.asarray(p_all, dtype=np.int32))
+        if po.size != count or (count and int(np.max(po + ns + 1)) > pa.size):
+            raise ValueError("p_off / p_all do not cover the chains")
+    st = load().mcm_parenthesize_batched(
+        count, _p_ptr(ns), po.ctypes.data_as(i64) if po is not None else None,
+        _p_ptr(pa) if pa is not None else None, tab_off.ctypes.data_as(i64),
+        ctypes.c_void_p(s_all.data_ptr()), node_off.ctypes.data_as(i64),
+        ctypes.c_void_p(lo_all.data_ptr()), ctypes.c_void_p(hi_all.data_ptr()),
+        _ptr_or_null(cost_all), ctypes.c_void_p(_stream_handle(stream)))
+    if st != OK:
+        raise MCMError(st, "mcm_parenthesize_batched")
+
+
+def node_offsets(ns) -> np.ndarray:
+    """Packed offsets of n-1 product entries per chain, one after another."""
+    ns = np.asarray(ns, dtype=np.int64)
+    off = np.zeros(ns.size, dtype=np.int64)
+    if ns.size > 1:
+        off[1:] = np.cumsum(ns[:-1] - 1)
+    return off
 
 
 def table_offsets(ns) -> np.ndarray:

@@ -135,6 +135,29 @@ struct BulkLayout {
 // pd[t] = p[t] for t < count, on the device.
 mcm_status widen_dims(const int32_t *p, double *pd, size_t count, hipStream_t stream);
 
+// ------------------------------------------------------------------------
+// Optimal order read back from split tables (k_paren.hip).
+// ------------------------------------------------------------------------
+struct ParenChain {     // one chain of a read-back launch
+    int64_t s_off;      // element offset of its n*n split table in s_all
+    int64_t p_off;      // element offset of its p[0] in the dims, -1 for none
+    int64_t g_off;      // element offset of its n-1 node entries in lo/hi
+    int64_t q_off;      // element offset of its n-1 task slots in the queue
+    int32_t n;          // matrices
+    int32_t cost_idx;   // its entry in cost_all, -1 for none
+};
+
+// Node intervals lo/hi (and the tree cost when cost_all is given) of every
+// chain; one workgroup per chain.  queue_all: sum of (n-1) int64 slots.
+mcm_status run_paren(const ParenChain *chains, int count, int max_n, const int32_t *s_all,
+                     const int32_t *p_all, int32_t *lo_all, int32_t *hi_all, int64_t *cost_all,
+                     int64_t *queue_all, hipStream_t stream);
+
+// Parenthesized text of one chain from its node intervals (counts: 2n
+// int32 workspace; text: its exact length plus a NUL).
+mcm_status run_paren_text(const int32_t *lo, const int32_t *hi, int n, int32_t *counts,
+                          char *text, hipStream_t stream);
+
 // Wavefront path (int64, any valid input).
 mcm_status run_wavefront(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int32_t *s,
                          hipStream_t stream);

@@ -111,3 +111,36 @@ def alternating(n: int, a: int = 1, b: int = 1024) -> np.ndarray:
 def tie_heavy(n: int, seed: int) -> np.ndarray:
     """Dims drawn from {1, 2}: many equal-cost splits."""
     return uniform_dims(n, 1, 2, seed)
+
+
+SPLIT_SHAPES = ("left", "right", "balanced", "zigzag", "random")
+
+
+def split_table(n: int, shape: str, seed: int = 0) -> np.ndarray:
+    """An n x n int32 table of valid splits (i <= s[i][j] < j above the
+    diagonal, -1 elsewhere) whose tree has a chosen shape, as input for
+    reading a tree back from a table:
+
+    left      s[i][j] = j-1: one long chain of left children
+    right     s[i][j] = i: one long chain of right children
+    balanced  s[i][j] = (i+j)//2
+    zigzag    alternates j-1 and i along the path from the root, so every
+              step of the path changes direction
+    random    iid uniform in [i, j-1] (PCG64 ``random`` doubles, row-major)
+    """
+    i = np.arange(n, dtype=np.int64)[:, None]
+    j = np.arange(n, dtype=np.int64)[None, :]
+    if shape == "left":
+        s = np.broadcast_to(j - 1, (n, n))
+    elif shape == "right":
+        s = np.broadcast_to(i, (n, n))
+    elif shape == "balanced":
+        s = (i + j) // 2
+    elif shape == "zigzag":
+        s = np.where((i + (n - 1 - j)) % 2 == 0, j - 1, i)
+    elif shape == "random":
+        u = np.random.default_rng(seed).random((n, n))
+        s = i + np.floor(u * np.maximum(j - i, 0)).astype(np.int64)
+    else:
+        raise ValueError(shape)
+    return np.where(j > i, s, -1).astype(np.int32)

@@ -151,3 +151,43 @@ def test_server_request_bytes(lib):
     # dims, m (8 B) and s (4 B) tables at least, 256-byte aligned
     assert small >= 2 * 2 * 12 and small % 256 == 0
     assert big >= 1000 * 1000 * 12 and big > small
+
+
+def test_parens_length_matches_oracle(lib):
+    from oracle import paren
+    for n in (1, 2, 9, 10, 11, 99, 100, 101, 999, 1000, 8192, 100000):
+        assert binding.parens_length(n) == paren.parens_length(n)
+    assert binding.parens_length(0) == -1
+
+
+def test_parenthesize_rejects_bad_input_before_device(lib):
+    # Host buffers stand in for device pointers; every case fails validation
+    # before anything is enqueued.
+    s = np.full(16, 7, dtype=np.int32)
+    lo = np.full(4, 7, dtype=np.int32)
+    cost = np.full(1, 7, dtype=np.int64)
+    p = np.array([3, 4, 5, 6, 7], dtype=np.int32)
+    pp = p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    vp = ctypes.c_void_p
+    f = lib.mcm_parenthesize
+    assert f(pp, 0, vp(s.ctypes.data), None, None, None, None, None) == binding.ERR_INVALID_ARG
+    assert f(pp, 4, None, None, None, None, None, None) == binding.ERR_INVALID_ARG
+    # lo without hi
+    assert f(pp, 4, vp(s.ctypes.data), vp(lo.ctypes.data), None, None, None,
+             None) == binding.ERR_INVALID_ARG
+    # a cost needs p
+    assert f(None, 4, vp(s.ctypes.data), None, None, vp(cost.ctypes.data), None,
+             None) == binding.ERR_INVALID_ARG
+    bad = np.array([3, 0, 5, 6, 7], dtype=np.int32)
+    assert f(bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 4, vp(s.ctypes.data), None,
+             None, vp(cost.ctypes.data), None, None) == binding.ERR_INVALID_ARG
+    assert (s == 7).all() and (lo == 7).all() and (cost == 7).all()
+    g = lib.mcm_parenthesize_batched
+    ns = np.array([4, 0], dtype=np.int32)
+    off = np.zeros(2, dtype=np.int64)
+    i64 = ctypes.POINTER(ctypes.c_int64)
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    assert g(0, None, None, None, None, None, None, None, None, None, None) == binding.OK
+    assert g(2, ns.ctypes.data_as(i32), None, None, off.ctypes.data_as(i64), vp(s.ctypes.data),
+             off.ctypes.data_as(i64), vp(lo.ctypes.data), vp(lo.ctypes.data), None,
+             None) == binding.ERR_INVALID_ARG
