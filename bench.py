@@ -122,6 +122,23 @@ def bench_batched(binding, workloads, torch, reps: int = 3):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         best = dt if best is None else min(best, dt)
+    # Read back all 4096 trees (with their costs) in one launch.
+    node_off = binding.node_offsets(b.ns)
+    g = int(node_off[-1] + b.ns[-1] - 1)
+    lo = torch.empty(g, dtype=torch.int32, device="cuda")
+    hi = torch.empty(g, dtype=torch.int32, device="cuda")
+    cost = torch.empty(b.ns.size, dtype=torch.int64, device="cuda")
+    rb = None
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        binding.parenthesize_batched_into(b.ns, off, s_all, node_off, lo, hi, p_off=b.p_off,
+                                          p_all=b.p_all, cost_all=cost)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rb = dt if rb is None else min(rb, dt)
+    roots = m_all[torch.as_tensor(off + b.ns.astype(np.int64) - 1, device="cuda")]
+    rb_ok = bool(torch.equal(roots, cost))
     chains = [binding.Chain(b.dims(i)) for i in range(b.ns.size)]
     views = [(m_all[int(off[i]):int(off[i]) + int(n) ** 2],
               s_all[int(off[i]):int(off[i]) + int(n) ** 2]) for i, n in enumerate(b.ns)]
@@ -140,7 +157,35 @@ def bench_batched(binding, workloads, torch, reps: int = 3):
             "split_evals_per_s": evals / best,
             "plain_instances_per_s": count / plain, "plain_ms": 1e3 * plain,
             "speedup_vs_plain": plain / best,
-            "note": "batched time includes the host dims upload of mcm_solve_batched"}
+            "readback_ms": 1e3 * rb, "readback_costs_equal_m0n": rb_ok,
+            "note": "batched time includes the host dims upload of mcm_solve_batched; "
+                    "readback is mcm_parenthesize_batched (trees and costs of all chains)"}
+
+
+def bench_reconstruction(binding, torch, p, m, s, reps: int = 5):
+    """Optimal order read back from the solved n = 8192 table on the device
+    (mcm_parenthesize: node intervals, tree cost and parenthesized text),
+    best of `reps` calls, wall time including the host side of the call."""
+    n = len(p) - 1
+    lo = torch.empty(n - 1, dtype=torch.int32, device="cuda")
+    hi = torch.empty(n - 1, dtype=torch.int32, device="cuda")
+    cost = torch.empty(1, dtype=torch.int64, device="cuda")
+    text = torch.empty(binding.parens_length(n) + 1, dtype=torch.uint8, device="cuda")
+    out = {}
+    for what, kw in (("tree_ms", dict(lo=lo, hi=hi)),
+                     ("tree_cost_text_ms", dict(lo=lo, hi=hi, cost=cost, p=p, text=text))):
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            binding.parenthesize_into(s, n, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        out[what] = 1e3 * best
+    out["cost_equals_m0n"] = int(cost.item()) == int(m.view(-1)[n - 1].item())
+    out["solve_fraction"] = None
+    return out
 
 
 def bench_serving(binding, workloads, torch, count: int, rate: float):
@@ -287,6 +332,9 @@ def main() -> int:
         "roofline": roofline,
         "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in prof.items()},
     }
+    rec = bench_reconstruction(binding, torch, p, m, s)
+    rec["solve_fraction"] = round(rec["tree_cost_text_ms"] / ms_per_step, 4)
+    out["reconstruction"] = rec
     chain.close()
     del m, s
     torch.cuda.synchronize()

@@ -24,6 +24,9 @@ HIPCC_FLAGS = [
     f"--offload-arch={ARCH}",
     "-O3",
     "-std=c++17",
+    # wave-wide atomics combine their lanes with a DPP scan (a few
+    # instructions) rather than a loop over the active lanes
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=DPP",
     "-fPIC",
     "-Wall",
     "-Wno-unused-result",

@@ -149,14 +149,16 @@ struct ParenChain {     // one chain of a read-back launch
 
 // Node intervals lo/hi (and the tree cost when cost_all is given) of every
 // chain; one workgroup per chain.  queue_all: sum of (n-1) int64 slots.
+// counts (one chain only, or null): 2n int32, receives per matrix the number
+// of nodes starting there, then the number ending there.
 mcm_status run_paren(const ParenChain *chains, int count, int max_n, const int32_t *s_all,
                      const int32_t *p_all, int32_t *lo_all, int32_t *hi_all, int64_t *cost_all,
-                     int64_t *queue_all, hipStream_t stream);
+                     int64_t *queue_all, int32_t *counts, hipStream_t stream);
 
-// Parenthesized text of one chain from its node intervals (counts: 2n
-// int32 workspace; text: its exact length plus a NUL).
-mcm_status run_paren_text(const int32_t *lo, const int32_t *hi, int n, int32_t *counts,
-                          char *text, hipStream_t stream);
+// Parenthesized text of one chain from its intervals and the counts run_paren
+// wrote (text: its exact length plus a NUL).
+mcm_status run_paren_text(const int32_t *lo, int n, const int32_t *counts, char *text,
+                          hipStream_t stream);
 
 // Wavefront path (int64, any valid input).
 mcm_status run_wavefront(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int32_t *s,

@@ -91,11 +91,11 @@ mcm_status mcm_parenthesize(const int32_t *p, int32_t n, const int32_t *s, int32
     const ParenChain *chain = (const ParenChain *)blob;
     const int32_t *p_dev = with_p ? (const int32_t *)((char *)blob + dims_at) : nullptr;
 
-    st = run_paren(chain, 1, n, s, p_dev, lo, hi, cost, queue, stream);
+    int32_t *counts = nullptr;
+    if (text != nullptr && !(counts = ws.get<int32_t>(2 * (size_t)n))) return MCM_ERR_NO_MEMORY;
+    st = run_paren(chain, 1, n, s, p_dev, lo, hi, cost, queue, counts, stream);
     if (st != MCM_OK || text == nullptr) return st;
-    int32_t *counts = ws.get<int32_t>(2 * (size_t)n);
-    if (!counts) return MCM_ERR_NO_MEMORY;
-    return run_paren_text(lo, hi, n, counts, text, stream);
+    return run_paren_text(lo, n, counts, text, stream);
 }
 
 mcm_status mcm_parenthesize_batched(int32_t count, const int32_t *n, const int64_t *p_off,
@@ -152,7 +152,7 @@ mcm_status mcm_parenthesize_batched(int32_t count, const int32_t *n, const int64
     ws.held.push_back(blob);
     const int32_t *p_dev = with_p ? (const int32_t *)((char *)blob + dims_at) : nullptr;
     return run_paren((const ParenChain *)blob, count, max_n, s_all, p_dev, lo_all, hi_all,
-                     cost_all, queue, stream);
+                     cost_all, queue, nullptr, stream);
 }
 
 }  // extern "C"

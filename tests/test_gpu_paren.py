@@ -103,6 +103,14 @@ def test_not_a_split_table():
     k = next(k for k in range(n - 1) if hi[k] - lo[k] >= 3 and (lo[k], hi[k]) != (0, n - 1))
     s[lo[k]][hi[k]] = hi[k] + 5
     assert _check(p, s, "bad inner") == -1
+    # entries above, at and below the cell's split range, on L and R walks
+    for seed in range(9):
+        s = workloads.split_table(n, "random", 40 + seed)
+        lo, hi, ok = paren.tree_from_splits(s, n)
+        ks = [k for k in range(n - 1) if hi[k] - lo[k] >= 2]
+        k = ks[(7 * seed) % len(ks)]
+        s[lo[k]][hi[k]] = [hi[k] + 5, lo[k] - 1, hi[k]][seed % 3]
+        assert _check(p, s, f"bad {seed}") == -1
     torch.cuda.synchronize()
 
 
