@@ -144,3 +144,32 @@ def split_table(n: int, shape: str, seed: int = 0) -> np.ndarray:
     else:
         raise ValueError(shape)
     return np.where(j > i, s, -1).astype(np.int32)
+
+
+# Simplified DP (S-DP) inputs.  The paper's Table I gives n and k ranges
+# only; each configuration here takes the top of a range.
+SDP_CONFIGS = {
+    "sdp_small": (1 << 15, 1 << 13),
+    "sdp_medium": (1 << 17, 1 << 15),
+    "sdp_large": (1 << 19, 1 << 17),
+}
+
+
+def sdp_instance(n: int, k: int, seed: int, kind: str = "random"):
+    """(offsets, init) for an S-DP table of n elements with k offsets.
+
+    random       k distinct offsets drawn without replacement from [1, 2k]
+                 (``choice(2k, k, replace=False) + 1``), sorted descending
+    consecutive  k, k-1, ..., 1 (the worst case of Fig. 4)
+    init: the a_1 preset values, iid in [0, 2^30) (drawn after the offsets).
+    """
+    rng = np.random.default_rng(seed)
+    if kind == "random":
+        a = np.sort(rng.choice(2 * k, size=k, replace=False) + 1)[::-1]
+    elif kind == "consecutive":
+        a = np.arange(k, 0, -1)
+    else:
+        raise ValueError(kind)
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    init = rng.integers(0, 1 << 30, size=int(a[0]), dtype=np.int32)
+    return a, init
