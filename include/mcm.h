@@ -218,6 +218,28 @@ mcm_status mcm_parenthesize_batched(int32_t count, const int32_t *n, const int64
                                     hipStream_t stream);
 
 /*
+ * The simplified DP problem (S-DP) of Section II-A, Definition 1: a
+ * one-dimensional table ST[0..n-1], offsets a_1 > a_2 > ... > a_k > 0 and a
+ * semigroup operator (x); ST[0..a_1-1] are preset and, Eq. (1),
+ *
+ *   ST[i] = ST[i - a_1] (x) ST[i - a_2] (x) ... (x) ST[i - a_k],   a_1 <= i < n.
+ *
+ *   a    host, k offsets, strictly decreasing, a[k-1] >= 1, a[0] <= n (read
+ *        before return).
+ *   op   MCM_SDP_MIN (the operator of the paper's Table I), MCM_SDP_MAX or
+ *        MCM_SDP_ADD (int32 addition modulo 2^32).
+ *   st   device, n int32, 4-byte aligned, caller-owned: st[0..a[0]-1] hold
+ *        the preset values on entry; the call writes st[a[0]..n-1] and
+ *        nothing else.  Results are exact and deterministic.
+ * Work is enqueued on `stream`; workspace (n int32 plus the offset tables)
+ * is stream-ordered.  MCM_ERR_INVALID_ARG for bad sizes, offsets, op or
+ * alignment (nothing enqueued); MCM_ERR_NO_MEMORY; MCM_ERR_DEVICE.
+ */
+typedef enum mcm_sdp_op { MCM_SDP_MIN = 0, MCM_SDP_MAX = 1, MCM_SDP_ADD = 2 } mcm_sdp_op;
+mcm_status mcm_sdp_solve(const int32_t *a, int32_t k, int32_t op, int32_t *st, int32_t n,
+                         hipStream_t stream);
+
+/*
  * Request server: continuous batching of many chains on one device.
  *
  * The server owns one device arena of `mem_budget` bytes from which each

@@ -36,8 +36,10 @@ EXPORTED = (
     "mcm_chain_destroy", "mcm_server_create", "mcm_server_submit", "mcm_server_poll",
     "mcm_server_release", "mcm_server_request_bytes", "mcm_server_stats", "mcm_server_destroy", "mcm_clock_now",
     "mcm_profile_enable", "mcm_profile_read", "mcm_parens_length", "mcm_parenthesize",
-    "mcm_parenthesize_batched",
+    "mcm_parenthesize_batched", "mcm_sdp_solve",
 )
+
+SDP_OPS = {"min": 0, "max": 1, "add": 2}
 
 
 class RequestInfo(ctypes.Structure):
@@ -129,6 +131,9 @@ def load() -> ctypes.CDLL:
             lib.mcm_parenthesize_batched.argtypes = [ctypes.c_int32, i32p, i64p, i32p, i64p, vp,
                                                      i64p, vp, vp, vp, vp]
             lib.mcm_parenthesize_batched.restype = ctypes.c_int
+            lib.mcm_sdp_solve.argtypes = [i32p, ctypes.c_int32, ctypes.c_int32, vp,
+                                          ctypes.c_int32, vp]
+            lib.mcm_sdp_solve.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -338,6 +343,21 @@ def parenthesize_batched_into(ns, tab_off, s_all, node_off, lo_all, hi_all, p_of
         _ptr_or_null(cost_all), ctypes.c_void_p(_stream_handle(stream)))
     if st != OK:
         raise MCMError(st, "mcm_parenthesize_batched")
+
+
+def sdp_solve_into(offsets, st, op: str = "min", stream=None) -> None:
+    """Enqueue mcm_sdp_solve: st is a contiguous CUDA int32 tensor of n
+    elements whose first offsets[0] entries hold the preset values."""
+    import torch
+    a = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32))
+    if a.ndim != 1:
+        raise ValueError("offsets must be one-dimensional")
+    if not (st.is_cuda and st.dtype == torch.int32 and st.is_contiguous()):
+        raise TypeError("st must be a contiguous CUDA int32 tensor")
+    rc = load().mcm_sdp_solve(_p_ptr(a), a.size, SDP_OPS[op], ctypes.c_void_p(st.data_ptr()),
+                              st.numel(), ctypes.c_void_p(_stream_handle(stream)))
+    if rc != OK:
+        raise MCMError(rc, "mcm_sdp_solve")
 
 
 def node_offsets(ns) -> np.ndarray:

@@ -1,0 +1,202 @@
+// The simplified DP problem (S-DP) of Section II-A, Definition 1:
+//
+//   ST[i] = ST[i - a_1] (x) ST[i - a_2] (x) ... (x) ST[i - a_k],   i >= a_1,
+//
+// with ST[0..a_1-1] preset, a_1 > ... > a_k > 0, and (x) one of minimum (the
+// operator of the paper's Table I), maximum or addition modulo 2^32, on int32.
+//
+// The computed range [a_1, n) is cut into blocks of B elements.  For an
+// element i = t + r of the block starting at t, the offsets a > r reach
+// before the block, so once the earlier blocks are final all of those terms
+// can be folded at once, across the whole device ("far" kernel).  The rest,
+// a <= r, read the block itself; they are folded by one workgroup walking the
+// block in sub-blocks of 64 ("near" kernel):
+//   - terms whose source lies in an earlier sub-block are folded in parallel
+//     (16 threads per element, a prefix count table giving each element its
+//     range of offsets);
+//   - terms inside the sub-block (offsets below 64) are folded by one wave
+//     whose lane l holds element l: at step r' lane r' is final, and every
+//     lane l with l - r' among the offsets folds it in, a register update per
+//     step instead of a memory round trip.
+// The paper's pipeline (Fig. 2) instead assigns one thread per offset and
+// advances one element per step; that keeps k threads busy, while this
+// layout spreads the bulk of the work (the far terms) over all CUs and keeps
+// only a 64-wide dependency chain on one wave.
+#include "mcm_internal.h"
+
+namespace mcm {
+namespace {
+
+constexpr int kFarTile = 256;        // targets per far workgroup (one per thread)
+constexpr int kNearThreads = 1024;
+
+template <int OP>
+__device__ __forceinline__ int32_t sdp_op(int32_t x, int32_t y)
+{
+    if constexpr (OP == SDP_MIN) return min(x, y);
+    else if constexpr (OP == SDP_MAX) return max(x, y);
+    else return (int32_t)((uint32_t)x + (uint32_t)y);
+}
+
+template <int OP>
+__device__ __forceinline__ int32_t sdp_identity()
+{
+    if constexpr (OP == SDP_MIN) return INT32_MAX;
+    else if constexpr (OP == SDP_MAX) return INT32_MIN;
+    else return 0;
+}
+
+template <int OP>
+__device__ __forceinline__ void sdp_atomic(int32_t *p, int32_t v)
+{
+    if constexpr (OP == SDP_MIN) atomicMin(p, v);
+    else if constexpr (OP == SDP_MAX) atomicMax(p, v);
+    else atomicAdd(p, v);
+}
+
+template <int OP>
+__global__ __launch_bounds__(256) void k_sdp_fill(int32_t *__restrict__ part, int64_t count)
+{
+    for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < count;
+         x += (int64_t)gridDim.x * 256)
+        part[x] = sdp_identity<OP>();
+}
+
+// Far terms of block [t, tend): part[i] (x)= ST[i - a_j] for every a_j > i - t.
+// Workgroup (tile, chunk): targets t0 .. t0+255 against offsets a[j0..j1),
+// whose sources, a span of at most kFarTile + span_max elements, are staged
+// into LDS first.  chunks: (j0, j1) pairs.
+template <int OP>
+__global__ __launch_bounds__(kFarTile) void k_sdp_far(const int32_t *__restrict__ st,
+                                                      int32_t *__restrict__ part,
+                                                      const int32_t *__restrict__ a,
+                                                      const int2 *__restrict__ chunks,
+                                                      int nchunks, int t, int tend)
+{
+    extern __shared__ int32_t lds[];
+    const int tile = blockIdx.x / nchunks;
+    const int2 ch = chunks[blockIdx.x % nchunks];
+    const int t0 = t + tile * kFarTile;
+    if (t0 >= tend) return;
+    const int amax = a[ch.x], amin = a[ch.y - 1];
+    if (amax <= t0 - t) return;                  // no offset reaches before the block
+    const int nj = ch.y - ch.x;
+    int32_t *offs = lds;                          // nj offsets, descending
+    int32_t *src = lds + ((nj + 3) & ~3);         // ST[lo .. hi]
+    const int lo = t0 - amax;
+    const int hi = min(t0 + kFarTile, tend) - 1 - amin;
+    const int tid = threadIdx.x;
+    for (int x = tid; x < nj; x += kFarTile) offs[x] = a[ch.x + x];
+    for (int x = tid; x <= hi - lo; x += kFarTile) src[x] = st[lo + x];
+    __syncthreads();
+    const int i = t0 + tid;
+    if (i >= tend) return;
+    const int r = i - t;
+    const int base = i - lo;
+    int32_t acc = sdp_identity<OP>();
+    int x = 0;
+    // Offsets are descending: the valid ones (a_j > r) are a prefix.
+    for (; x + 4 <= nj && offs[x + 3] > r; x += 4) {
+        acc = sdp_op<OP>(acc, src[base - offs[x]]);
+        acc = sdp_op<OP>(acc, src[base - offs[x + 1]]);
+        acc = sdp_op<OP>(acc, src[base - offs[x + 2]]);
+        acc = sdp_op<OP>(acc, src[base - offs[x + 3]]);
+    }
+    for (; x < nj && offs[x] > r; ++x) acc = sdp_op<OP>(acc, src[base - offs[x]]);
+    if (x > 0) sdp_atomic<OP>(part + i, acc);
+}
+
+// Near terms of block [t, tend) (a_j <= i - t), then the block's final
+// values to st.  near_a: the offsets below B, ascending; cnt_le[x]: how many
+// of them are <= x (x < B); seq_mask[l]: bit r' set when l - r' is an offset
+// (0 <= r' < l < 64).  One workgroup; LDS holds the block.
+template <int OP>
+__global__ __launch_bounds__(kNearThreads) void k_sdp_near(int32_t *__restrict__ st,
+                                                           const int32_t *__restrict__ part,
+                                                           const int32_t *__restrict__ near_a,
+                                                           int kn,
+                                                           const int32_t *__restrict__ cnt_le,
+                                                           const uint64_t *__restrict__ seq_mask,
+                                                           int t, int tend, int B)
+{
+    extern __shared__ int32_t lds[];
+    int32_t *blk = lds;                   // B values of the block
+    int32_t *cle = lds + B;               // B prefix counts
+    int32_t *na = lds + 2 * B;            // kn offsets (< B), ascending
+    const int tid = threadIdx.x;
+    const int len = tend - t;
+    for (int x = tid; x < B; x += kNearThreads) {
+        blk[x] = x < len ? part[t + x] : sdp_identity<OP>();
+        cle[x] = cnt_le[x];
+    }
+    for (int x = tid; x < kn; x += kNearThreads) na[x] = near_a[x];
+    const int lane = tid & 63;
+    const uint64_t gm = tid < 64 ? seq_mask[lane] : 0;
+    __syncthreads();
+    const int nsub = (len + 63) / 64;
+    const int l = tid >> 4, g = tid & 15;
+    for (int s = 0; s < nsub; ++s) {
+        if (s > 0) {
+            // Sources in earlier sub-blocks: offsets in [l+1, r].
+            const int r = 64 * s + l;
+            int32_t acc = sdp_identity<OP>();
+            for (int j = cle[l] + g; j < cle[r]; j += 16) acc = sdp_op<OP>(acc, blk[r - na[j]]);
+            for (int off = 8; off > 0; off >>= 1) acc = sdp_op<OP>(acc, __shfl_xor(acc, off, 16));
+            if (g == 0) blk[r] = sdp_op<OP>(blk[r], acc);
+        }
+        __syncthreads();
+        if (tid < 64) {
+            // Sources inside the sub-block: lane r' is final at step r'.
+            int32_t v = blk[64 * s + lane];
+#pragma unroll 3
+            for (int rp = 0; rp < 63; ++rp) {
+                const int32_t w = __builtin_amdgcn_readlane(v, rp);
+                if ((gm >> rp) & 1) v = sdp_op<OP>(v, w);
+            }
+            blk[64 * s + lane] = v;
+            if (64 * s + lane < len) st[t + 64 * s + lane] = v;
+        }
+        __syncthreads();
+    }
+}
+
+template <int OP>
+mcm_status sdp_launch(const SdpPlan &pl, int32_t *st, hipStream_t stream)
+{
+    const int64_t cnt = (int64_t)pl.n - pl.a1;
+    {
+        const int64_t want = (cnt + 255) / 256;
+        const unsigned blocks = (unsigned)(want < 4096 ? (want < 1 ? 1 : want) : 4096);
+        hipLaunchKernelGGL(k_sdp_fill<OP>, dim3(blocks), dim3(256), 0, stream, pl.part + pl.a1,
+                           cnt);
+        if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
+    }
+    const size_t far_lds = (size_t)(((pl.chunk_max + 3) & ~3) + kFarTile + pl.span_max) * 4;
+    const size_t near_lds = (size_t)(2 * pl.B + pl.kn) * 4;
+    const int tiles = (pl.B + kFarTile - 1) / kFarTile;
+    for (int64_t t = pl.a1; t < pl.n; t += pl.B) {
+        const int tend = (int)(t + pl.B < pl.n ? t + pl.B : pl.n);
+        hipLaunchKernelGGL(k_sdp_far<OP>, dim3((unsigned)(tiles * pl.nchunks)), dim3(kFarTile),
+                           far_lds, stream, st, pl.part, pl.a, pl.chunks, pl.nchunks, (int)t,
+                           tend);
+        hipLaunchKernelGGL(k_sdp_near<OP>, dim3(1), dim3(kNearThreads), near_lds, stream, st,
+                           pl.part, pl.near_a, pl.kn, pl.cnt_le, pl.seq_mask, (int)t, tend, pl.B);
+        if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
+    }
+    return MCM_OK;
+}
+
+}  // namespace
+
+mcm_status run_sdp(const SdpPlan &pl, int op, int32_t *st, hipStream_t stream)
+{
+    if (pl.a1 >= pl.n) return MCM_OK;
+    switch (op) {
+    case SDP_MIN: return sdp_launch<SDP_MIN>(pl, st, stream);
+    case SDP_MAX: return sdp_launch<SDP_MAX>(pl, st, stream);
+    case SDP_ADD: return sdp_launch<SDP_ADD>(pl, st, stream);
+    default: return MCM_ERR_INVALID_ARG;
+    }
+}
+
+}  // namespace mcm

@@ -160,6 +160,26 @@ mcm_status run_paren(const ParenChain *chains, int count, int max_n, const int32
 mcm_status run_paren_text(const int32_t *lo, int n, const int32_t *counts, char *text,
                           hipStream_t stream);
 
+// ------------------------------------------------------------------------
+// Simplified DP (k_sdp.hip).
+// ------------------------------------------------------------------------
+enum { SDP_MIN = 0, SDP_MAX = 1, SDP_ADD = 2 };
+
+struct SdpPlan {
+    int32_t n = 0, a1 = 0;        // table size, largest offset
+    int32_t B = 0;                // block of elements per far/near launch pair
+    const int32_t *a = nullptr;   // device, k offsets descending
+    const int2 *chunks = nullptr; // device, (j0, j1) offset chunks of the far kernel
+    int32_t nchunks = 0, chunk_max = 0, span_max = 0;
+    const int32_t *near_a = nullptr;     // device, offsets < B ascending
+    int32_t kn = 0;
+    const int32_t *cnt_le = nullptr;     // device, B prefix counts of near_a
+    const uint64_t *seq_mask = nullptr;  // device, 64 masks of offsets < 64
+    int32_t *part = nullptr;      // device workspace, n partial folds
+};
+
+mcm_status run_sdp(const SdpPlan &plan, int op, int32_t *st, hipStream_t stream);
+
 // Wavefront path (int64, any valid input).
 mcm_status run_wavefront(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int32_t *s,
                          hipStream_t stream);

@@ -191,3 +191,22 @@ def test_parenthesize_rejects_bad_input_before_device(lib):
     assert g(2, ns.ctypes.data_as(i32), None, None, off.ctypes.data_as(i64), vp(s.ctypes.data),
              off.ctypes.data_as(i64), vp(lo.ctypes.data), vp(lo.ctypes.data), None,
              None) == binding.ERR_INVALID_ARG
+
+
+def test_sdp_rejects_bad_input_before_device(lib):
+    st = np.full(64, 7, dtype=np.int32)
+    vp = ctypes.c_void_p(st.ctypes.data)
+    f = lib.mcm_sdp_solve
+
+    def call(a, op=0, n=64):
+        arr = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+        return f(arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), arr.size, op, vp, n, None)
+
+    assert call([3, 3]) == binding.ERR_INVALID_ARG        # not strictly decreasing
+    assert call([3, 0]) == binding.ERR_INVALID_ARG        # a_k < 1
+    assert call([65]) == binding.ERR_INVALID_ARG          # a_1 > n
+    assert call([4, 1], op=7) == binding.ERR_INVALID_ARG  # unknown operator
+    assert call([4, 1], n=0) == binding.ERR_INVALID_ARG
+    assert f(None, 2, 0, vp, 64, None) == binding.ERR_INVALID_ARG
+    assert call([64]) == binding.OK                       # a_1 = n: nothing to do
+    assert (st == 7).all()
