@@ -132,6 +132,7 @@ __global__ __launch_bounds__(kNearThreads) void k_sdp_near(int32_t *__restrict__
     for (int x = tid; x < kn; x += kNearThreads) na[x] = near_a[x];
     const int lane = tid & 63;
     const uint64_t gm = tid < 64 ? seq_mask[lane] : 0;
+    const uint32_t gm_lo = (uint32_t)gm, gm_hi = (uint32_t)(gm >> 32);
     __syncthreads();
     const int nsub = (len + 63) / 64;
     const int l = tid >> 4, g = tid & 15;
@@ -140,18 +141,34 @@ __global__ __launch_bounds__(kNearThreads) void k_sdp_near(int32_t *__restrict__
             // Sources in earlier sub-blocks: offsets in [l+1, r].
             const int r = 64 * s + l;
             int32_t acc = sdp_identity<OP>();
-            for (int j = cle[l] + g; j < cle[r]; j += 16) acc = sdp_op<OP>(acc, blk[r - na[j]]);
+            const int jend = cle[r];
+            int j = cle[l] + g;
+            // Four independent offset reads, then four source reads, per trip.
+            for (; j + 48 < jend; j += 64) {
+                const int d0 = na[j], d1 = na[j + 16], d2 = na[j + 32], d3 = na[j + 48];
+                acc = sdp_op<OP>(acc, blk[r - d0]);
+                acc = sdp_op<OP>(acc, blk[r - d1]);
+                acc = sdp_op<OP>(acc, blk[r - d2]);
+                acc = sdp_op<OP>(acc, blk[r - d3]);
+            }
+            for (; j < jend; j += 16) acc = sdp_op<OP>(acc, blk[r - na[j]]);
             for (int off = 8; off > 0; off >>= 1) acc = sdp_op<OP>(acc, __shfl_xor(acc, off, 16));
             if (g == 0) blk[r] = sdp_op<OP>(blk[r], acc);
         }
         __syncthreads();
         if (tid < 64) {
-            // Sources inside the sub-block: lane r' is final at step r'.
+            // Sources inside the sub-block: lane r' is final at step r', and
+            // every lane l with l - r' among the offsets folds it in.
             int32_t v = blk[64 * s + lane];
-#pragma unroll 3
-            for (int rp = 0; rp < 63; ++rp) {
+#pragma unroll 4
+            for (int rp = 0; rp < 32; ++rp) {
                 const int32_t w = __builtin_amdgcn_readlane(v, rp);
-                if ((gm >> rp) & 1) v = sdp_op<OP>(v, w);
+                v = sdp_op<OP>(v, ((gm_lo >> rp) & 1) ? w : sdp_identity<OP>());
+            }
+#pragma unroll 4
+            for (int rp = 32; rp < 63; ++rp) {
+                const int32_t w = __builtin_amdgcn_readlane(v, rp);
+                v = sdp_op<OP>(v, ((gm_hi >> (rp - 32)) & 1) ? w : sdp_identity<OP>());
             }
             blk[64 * s + lane] = v;
             if (64 * s + lane < len) st[t + 64 * s + lane] = v;

@@ -11,7 +11,7 @@ using namespace mcm;
 namespace {
 
 constexpr int kSdpBlock = 2048;      // elements per far/near launch pair
-constexpr int kChunkMax = 2048;      // offsets per far workgroup
+constexpr int kChunkMax = 1024;      // offsets per far workgroup
 constexpr int kSpanMax = 8192 - 256; // a[j0] - a[j1-1] within a chunk
 
 size_t align8(size_t x) { return (x + 7) / 8 * 8; }
