@@ -12,8 +12,9 @@
 // a <= r, read the block itself; they are folded by one workgroup walking the
 // block in sub-blocks of 64 ("near" kernel):
 //   - terms whose source lies in an earlier sub-block are folded in parallel
-//     (16 threads per element, a prefix count table giving each element its
-//     range of offsets);
+//     (a prefix count table giving each element its range of offsets); those
+//     reaching before the previous sub-block run while that sub-block's own
+//     chain (below) is in progress, the rest right after it;
 //   - terms inside the sub-block (offsets below 64) are folded by one wave
 //     whose lane l holds element l: at step r' lane r' is final, and every
 //     lane l with l - r' among the offsets folds it in, a register update per
@@ -135,28 +136,11 @@ __global__ __launch_bounds__(kNearThreads) void k_sdp_near(int32_t *__restrict__
     const uint32_t gm_lo = (uint32_t)gm, gm_hi = (uint32_t)(gm >> 32);
     __syncthreads();
     const int nsub = (len + 63) / 64;
-    const int l = tid >> 4, g = tid & 15;
+    const int wave = tid >> 6;
     for (int s = 0; s < nsub; ++s) {
-        if (s > 0) {
-            // Sources in earlier sub-blocks: offsets in [l+1, r].
-            const int r = 64 * s + l;
-            int32_t acc = sdp_identity<OP>();
-            const int jend = cle[r];
-            int j = cle[l] + g;
-            // Four independent offset reads, then four source reads, per trip.
-            for (; j + 48 < jend; j += 64) {
-                const int d0 = na[j], d1 = na[j + 16], d2 = na[j + 32], d3 = na[j + 48];
-                acc = sdp_op<OP>(acc, blk[r - d0]);
-                acc = sdp_op<OP>(acc, blk[r - d1]);
-                acc = sdp_op<OP>(acc, blk[r - d2]);
-                acc = sdp_op<OP>(acc, blk[r - d3]);
-            }
-            for (; j < jend; j += 16) acc = sdp_op<OP>(acc, blk[r - na[j]]);
-            for (int off = 8; off > 0; off >>= 1) acc = sdp_op<OP>(acc, __shfl_xor(acc, off, 16));
-            if (g == 0) blk[r] = sdp_op<OP>(blk[r], acc);
-        }
-        __syncthreads();
-        if (tid < 64) {
+        // Here sub-block s holds every term but those whose source lies
+        // inside it.
+        if (wave == 0) {
             // Sources inside the sub-block: lane r' is final at step r', and
             // every lane l with l - r' among the offsets folds it in.
             int32_t v = blk[64 * s + lane];
@@ -172,6 +156,35 @@ __global__ __launch_bounds__(kNearThreads) void k_sdp_near(int32_t *__restrict__
             }
             blk[64 * s + lane] = v;
             if (64 * s + lane < len) st[t + 64 * s + lane] = v;
+        } else if (wave >= 8 && s + 1 < nsub) {
+            // Meanwhile, sub-block s+1 folds its sources before sub-block s
+            // (offsets in [l+65, r]), 8 threads per element.
+            const int u = tid - 512, l = u >> 3, g = u & 7;
+            const int r = 64 * (s + 1) + l;
+            int32_t acc = sdp_identity<OP>();
+            const int jend = cle[r];
+            int j = cle[l + 64] + g;
+            for (; j + 24 < jend; j += 32) {
+                const int d0 = na[j], d1 = na[j + 8], d2 = na[j + 16], d3 = na[j + 24];
+                acc = sdp_op<OP>(acc, blk[r - d0]);
+                acc = sdp_op<OP>(acc, blk[r - d1]);
+                acc = sdp_op<OP>(acc, blk[r - d2]);
+                acc = sdp_op<OP>(acc, blk[r - d3]);
+            }
+            for (; j < jend; j += 8) acc = sdp_op<OP>(acc, blk[r - na[j]]);
+            for (int off = 4; off > 0; off >>= 1) acc = sdp_op<OP>(acc, __shfl_xor(acc, off, 8));
+            if (g == 0) blk[r] = sdp_op<OP>(blk[r], acc);
+        }
+        __syncthreads();
+        if (s + 1 < nsub) {
+            // Then its sources in sub-block s, now final (offsets in
+            // [l+1, l+64]), 16 threads per element.
+            const int l = tid >> 4, g = tid & 15;
+            const int r = 64 * (s + 1) + l;
+            int32_t acc = sdp_identity<OP>();
+            for (int j = cle[l] + g; j < cle[l + 64]; j += 16) acc = sdp_op<OP>(acc, blk[r - na[j]]);
+            for (int off = 8; off > 0; off >>= 1) acc = sdp_op<OP>(acc, __shfl_xor(acc, off, 16));
+            if (g == 0) blk[r] = sdp_op<OP>(blk[r], acc);
         }
         __syncthreads();
     }
