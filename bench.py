@@ -188,6 +188,36 @@ def bench_reconstruction(binding, torch, p, m, s, reps: int = 5):
     return out
 
 
+# Table I of the paper (PIPELINE column, ms, GTX TITAN Black, averages over
+# n and k in each range): context for the S-DP timings, not a target.
+SDP_PAPER_PIPELINE_MS = {"sdp_small": 78, "sdp_medium": 386, "sdp_large": 2408}
+
+
+def bench_sdp(binding, workloads, torch, reps: int = 3):
+    """The simplified DP problem (Section II-A) at the top of each n / k
+    range of Table I, minimum operator, random offsets (seed 12)."""
+    out = {}
+    for name, (n, k) in workloads.SDP_CONFIGS.items():
+        a, init = workloads.sdp_instance(n, k, 12)
+        st = torch.zeros(n, dtype=torch.int32, device="cuda")
+        st[:int(a[0])] = torch.from_numpy(init).cuda()
+        binding.sdp_solve_into(a, st, "min")
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            binding.sdp_solve_into(a, st, "min")
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        pairs = float(n - int(a[0])) * k
+        out[name] = {"n": n, "k": k, "a1": int(a[0]), "ms": 1e3 * best,
+                     "terms_per_s": pairs / best,
+                     "paper_pipeline_ms_gtx_titan_black": SDP_PAPER_PIPELINE_MS[name]}
+    return {"workload": "S-DP, min, k offsets drawn from [1, 2k], n and k at the top of "
+                        "each Table I range (seed 12)", "configs": out}
+
+
 def bench_serving(binding, workloads, torch, count: int, rate: float):
     """Open-loop Poisson stream (seed 4, n log-uniform in [8, 4096], dims in
     [1, 1024]): continuous-batching server against plain FIFO solves."""
@@ -239,6 +269,7 @@ def main() -> int:
                     help="one solve plus a 1 GiB copy, for rocprofv3 --pmc runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--no-sdp", action="store_true", help="skip the S-DP section")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-rate", type=float, default=600.0, help="Poisson arrivals per second")
     args = ap.parse_args()
@@ -344,6 +375,8 @@ def main() -> int:
     if not args.no_serving:
         out["serving"] = bench_serving(binding, workloads, torch, args.serve_requests,
                                        args.serve_rate)
+    if not args.no_sdp:
+        out["sdp"] = bench_sdp(binding, workloads, torch)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(out), flush=True)
