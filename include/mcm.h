@@ -240,6 +240,35 @@ mcm_status mcm_sdp_solve(const int32_t *a, int32_t k, int32_t op, int32_t *st, i
                          hipStream_t stream);
 
 /*
+ * Optimal binary search tree: an interval DP with the split shape of MCM,
+ * from the textbook the paper takes MCM from, for the paper's closing aim
+ * (end of Section IV) of carrying its technique to more general DP
+ * problems.  Keys k_1 < ... < k_n with search weights p_1..p_n and gaps
+ * d_0..d_n (unsuccessful searches) with weights q_0..q_n; the cost of a
+ * tree is the sum of (depth + 1) times the weight of every key and gap.
+ * Cells are intervals of gaps: for 0 <= a <= b <= n, cell (a, b) is the
+ * subtree over keys a+1..b, and
+ *
+ *   e[a][a] = q_a
+ *   e[a][b] = min_{a <= k < b} e[a][k] + e[k+1][b] + W(a, b)
+ *   W(a, b) = q_a + ... + q_b + p_{a+1} + ... + p_b
+ *
+ *   p         host, n int32 key weights p_1..p_n (>= 0; NULL when n = 0).
+ *   q         host, n+1 int32 gap weights q_0..q_n (>= 0).
+ *   n         number of keys, 0 <= n <= 2^30.
+ *   e_out     device, (n+1)*(n+1) int64, row-major, symmetric: e_out[a][b] =
+ *             e_out[b][a] = e[a][b]; the optimal tree's cost is e_out[0][n].
+ *   root_out  device, (n+1)*(n+1) int32: for a < b the smallest optimal
+ *             root key (1-based, in a+1..b); -1 for a >= b.
+ * Validation (host, before anything is enqueued): negative weights give
+ * MCM_ERR_INVALID_ARG; 2 (n+1) (2n+1) max(p, q) >= 4.6e18 gives
+ * MCM_ERR_OVERFLOW.  Exact int64, deterministic; stream semantics as in
+ * mcm_solve.  Filled by the wavefront kernels (one launch per diagonal).
+ */
+mcm_status mcm_obst_solve(const int32_t *p, const int32_t *q, int32_t n, int64_t *e_out,
+                          int32_t *root_out, hipStream_t stream);
+
+/*
  * Request server: continuous batching of many chains on one device.
  *
  * The server owns one device arena of `mem_budget` bytes from which each

@@ -180,6 +180,11 @@ struct SdpPlan {
 
 mcm_status run_sdp(const SdpPlan &plan, int op, int32_t *st, hipStream_t stream);
 
+// Optimal binary search tree over L = n+1 gaps (k_interval.hip): q (L
+// int32), W(a, b) = hi_w[b] - lo_w[a]; e and root are L x L.
+mcm_status run_obst(const int32_t *q, const int64_t *hi_w, const int64_t *lo_w, int32_t L,
+                    int64_t *e, int32_t *root, hipStream_t stream);
+
 // Wavefront path (int64, any valid input).
 mcm_status run_wavefront(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int32_t *s,
                          hipStream_t stream);

@@ -210,3 +210,24 @@ def test_sdp_rejects_bad_input_before_device(lib):
     assert f(None, 2, 0, vp, 64, None) == binding.ERR_INVALID_ARG
     assert call([64]) == binding.OK                       # a_1 = n: nothing to do
     assert (st == 7).all()
+
+
+def test_obst_rejects_bad_input_before_device(lib):
+    e = np.full(16, 7, dtype=np.int64)
+    r = np.full(16, 7, dtype=np.int32)
+    ep, rp = ctypes.c_void_p(e.ctypes.data), ctypes.c_void_p(r.ctypes.data)
+    i32 = ctypes.POINTER(ctypes.c_int32)
+
+    def call(p, q, n):
+        pa = np.ascontiguousarray(np.asarray(p, dtype=np.int32))
+        qa = np.ascontiguousarray(np.asarray(q, dtype=np.int32))
+        return lib.mcm_obst_solve(pa.ctypes.data_as(i32), qa.ctypes.data_as(i32), n, ep, rp, None)
+
+    assert call([1, -1, 2], [1, 1, 1, 1], 3) == binding.ERR_INVALID_ARG
+    assert call([1, 1, 2], [1, 1, -1, 1], 3) == binding.ERR_INVALID_ARG
+    assert call([1], [1, 1], -1) == binding.ERR_INVALID_ARG
+    assert lib.mcm_obst_solve(None, None, 0, ep, rp, None) == binding.ERR_INVALID_ARG
+    big = (1 << 31) - 1
+    n = 1 << 20
+    assert call(np.full(n, big), np.full(n + 1, big), n) == binding.ERR_OVERFLOW
+    assert (e == 7).all() and (r == 7).all()
