@@ -218,6 +218,27 @@ def bench_sdp(binding, workloads, torch, reps: int = 3):
                         "each Table I range (seed 12)", "configs": out}
 
 
+def bench_obst(binding, torch, n: int = 8192, reps: int = 2):
+    """Optimal binary search tree over n keys (key and gap weights iid in
+    [0, 2^16), seed 5), the interval DP of the same split shape."""
+    rng = np.random.default_rng(5)
+    p = rng.integers(0, 1 << 16, size=n).astype(np.int32)
+    q = rng.integers(0, 1 << 16, size=n + 1).astype(np.int32)
+    e, r = binding.obst_solve(p, q)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        e, r = binding.obst_solve(p, q)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    L = n + 1
+    evals = (L ** 3 - L) / 6
+    return {"workload": f"optimal BST, n={n} keys, weights uniform [0, 2^16), seed 5",
+            "ms": 1e3 * best, "split_evals_per_s": evals / best, "path": "wavefront (int64)"}
+
+
 def bench_serving(binding, workloads, torch, count: int, rate: float):
     """Open-loop Poisson stream (seed 4, n log-uniform in [8, 4096], dims in
     [1, 1024]): continuous-batching server against plain FIFO solves."""
@@ -270,6 +291,7 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the batched section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--no-sdp", action="store_true", help="skip the S-DP section")
+    ap.add_argument("--no-obst", action="store_true", help="skip the optimal-BST section")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-rate", type=float, default=600.0, help="Poisson arrivals per second")
     args = ap.parse_args()
@@ -377,6 +399,8 @@ def main() -> int:
                                        args.serve_rate)
     if not args.no_sdp:
         out["sdp"] = bench_sdp(binding, workloads, torch)
+    if not args.no_obst:
+        out["obst"] = bench_obst(binding, torch)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(out), flush=True)
