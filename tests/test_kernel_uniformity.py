@@ -43,4 +43,4 @@ def test_walk_kernel_loops_are_uniform(tmp_path):
         cycles = m.group(1).strip().splitlines() if m else []
         # the two grid-stride initialisation loops and the final cost loop
         assert len(cycles) <= 3, cycles
-        assert all(c.startswith("depth=1") for c in cycles), cycles
+        assert all(c.strip().startswith("depth=1") for c in cycles), cycles
