@@ -263,10 +263,18 @@ mcm_status mcm_sdp_solve(const int32_t *a, int32_t k, int32_t op, int32_t *st, i
  * Validation (host, before anything is enqueued): negative weights give
  * MCM_ERR_INVALID_ARG; 2 (n+1) (2n+1) max(p, q) >= 4.6e18 gives
  * MCM_ERR_OVERFLOW.  Exact int64, deterministic; stream semantics as in
- * mcm_solve.  Filled by the wavefront kernels (one launch per diagonal).
+ * mcm_solve.
  */
 mcm_status mcm_obst_solve(const int32_t *p, const int32_t *q, int32_t n, int64_t *e_out,
                           int32_t *root_out, hipStream_t stream);
+
+/* mcm_obst_solve with an explicit kernel path (mcm_algo): the tiled kernels
+ * in their weight-interval mode (W added once per cell after its minimum;
+ * needs 2 (n+1) (2n+1) max(p, q) < 2^46, else MCM_ERR_UNSUPPORTED), or the
+ * int64 diagonal launches, which accept every valid input.  AUTO takes the
+ * tiled path when it accepts the input.  Both return the same bytes. */
+mcm_status mcm_obst_solve_algo(const int32_t *p, const int32_t *q, int32_t n, int64_t *e_out,
+                               int32_t *root_out, int32_t algo, hipStream_t stream);
 
 /*
  * Request server: continuous batching of many chains on one device.

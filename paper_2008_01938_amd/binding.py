@@ -37,6 +37,7 @@ EXPORTED = (
     "mcm_server_release", "mcm_server_request_bytes", "mcm_server_stats", "mcm_server_destroy", "mcm_clock_now",
     "mcm_profile_enable", "mcm_profile_read", "mcm_parens_length", "mcm_parenthesize",
     "mcm_parenthesize_batched", "mcm_sdp_solve", "mcm_obst_solve",
+    "mcm_obst_solve_algo",
 )
 
 SDP_OPS = {"min": 0, "max": 1, "add": 2}
@@ -136,6 +137,9 @@ def load() -> ctypes.CDLL:
             lib.mcm_sdp_solve.restype = ctypes.c_int
             lib.mcm_obst_solve.argtypes = [i32p, i32p, ctypes.c_int32, vp, vp, vp]
             lib.mcm_obst_solve.restype = ctypes.c_int
+            lib.mcm_obst_solve_algo.argtypes = [i32p, i32p, ctypes.c_int32, vp, vp,
+                                                ctypes.c_int32, vp]
+            lib.mcm_obst_solve_algo.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -362,9 +366,9 @@ def sdp_solve_into(offsets, st, op: str = "min", stream=None) -> None:
         raise MCMError(rc, "mcm_sdp_solve")
 
 
-def obst_solve(p, q, device="cuda", stream=None):
-    """Optimal binary search tree (mcm_obst_solve): returns the (n+1) x (n+1)
-    CUDA tensors (e int64, root int32); enqueued on `stream`."""
+def obst_solve(p, q, algo: int | str = ALGO_AUTO, device="cuda", stream=None):
+    """Optimal binary search tree (mcm_obst_solve_algo): returns the
+    (n+1) x (n+1) CUDA tensors (e int64, root int32); enqueued on `stream`."""
     import torch
     pa = np.ascontiguousarray(np.asarray(p, dtype=np.int32))
     qa = np.ascontiguousarray(np.asarray(q, dtype=np.int32))
@@ -373,11 +377,14 @@ def obst_solve(p, q, device="cuda", stream=None):
         raise ValueError("need n+1 gap weights")
     e = torch.empty((n + 1, n + 1), dtype=torch.int64, device=device)
     root = torch.empty((n + 1, n + 1), dtype=torch.int32, device=device)
-    rc = load().mcm_obst_solve(_p_ptr(pa) if n else None, _p_ptr(qa), n,
-                               ctypes.c_void_p(e.data_ptr()), ctypes.c_void_p(root.data_ptr()),
-                               ctypes.c_void_p(_stream_handle(stream)))
+    if isinstance(algo, str):
+        algo = ALGOS[algo]
+    rc = load().mcm_obst_solve_algo(_p_ptr(pa) if n else None, _p_ptr(qa), n,
+                                    ctypes.c_void_p(e.data_ptr()),
+                                    ctypes.c_void_p(root.data_ptr()), int(algo),
+                                    ctypes.c_void_p(_stream_handle(stream)))
     if rc != OK:
-        raise MCMError(rc, "mcm_obst_solve")
+        raise MCMError(rc, "mcm_obst_solve_algo")
     return e, root
 
 

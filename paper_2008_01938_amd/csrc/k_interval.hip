@@ -82,6 +82,16 @@ __global__ __launch_bounds__(kIvBlock) void k_obst_init(const int32_t *__restric
     }
 }
 
+// The tiled path writes the split k (a gap index); the root key is k + 1.
+__global__ __launch_bounds__(kIvBlock) void k_obst_root(int32_t *__restrict__ root, int64_t total)
+{
+    for (int64_t idx = (int64_t)blockIdx.x * kIvBlock + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kIvBlock) {
+        const int32_t v = root[idx];
+        if (v >= 0) root[idx] = v + 1;
+    }
+}
+
 template <int G>
 hipError_t launch_obst(const int64_t *hi_w, const int64_t *lo_w, int32_t L, int32_t d,
                        int64_t *e, int32_t *root, hipStream_t stream)
@@ -118,6 +128,19 @@ mcm_status run_obst(const int32_t *q, const int64_t *hi_w, const int64_t *lo_w, 
         if (err != hipSuccess) return MCM_ERR_DEVICE;
     }
     return MCM_OK;
+}
+
+}  // namespace mcm
+
+namespace mcm {
+
+mcm_status run_obst_root(int32_t *root, int32_t L, hipStream_t stream)
+{
+    const int64_t total = (int64_t)L * L;
+    const int64_t want = (total + kIvBlock - 1) / kIvBlock;
+    const unsigned blocks = (unsigned)(want < 4096 ? (want < 1 ? 1 : want) : 4096);
+    hipLaunchKernelGGL(k_obst_root, dim3(blocks), dim3(kIvBlock), 0, stream, root, total);
+    return hipGetLastError() == hipSuccess ? MCM_OK : MCM_ERR_DEVICE;
 }
 
 }  // namespace mcm

@@ -76,11 +76,18 @@ __device__ __forceinline__ int find_seg(const TileSeg *__restrict__ seg, int nse
 // cells of the same tile.  Local diagonals dd = 1..nI-1 in order; four
 // lanes per cell, lexicographic (cost, k) reduction.  int64 arithmetic.
 // ------------------------------------------------------------------------
+// OB: the optimal-BST weights (one chain; p_all then holds zeros): the
+// diagonal holds the gap weights q and every cell gains W(i, j) = hi[j] -
+// lo[i] after its minimum.
+template <bool OB>
 __global__ __launch_bounds__(NTH) void k_tri(const TileChain *__restrict__ chains,
                                              const TileSeg *__restrict__ segs, int nseg,
                                              const int32_t *__restrict__ p_all,
                                              int64_t *__restrict__ m_all,
-                                             int32_t *__restrict__ s_all)
+                                             int32_t *__restrict__ s_all,
+                                             const int64_t *__restrict__ ob_hi,
+                                             const int64_t *__restrict__ ob_lo,
+                                             const int32_t *__restrict__ ob_q)
 {
     __shared__ int64_t tv[T][T + 1];
     __shared__ int32_t sv[T][T + 1];
@@ -95,7 +102,7 @@ __global__ __launch_bounds__(NTH) void k_tri(const TileChain *__restrict__ chain
     const int base = (blockIdx.x - sg.first) * T;
     const int nI = min(T, n - base);
     for (int q = tid; q <= nI; q += NTH) ps[q] = p[base + q];
-    for (int r = tid; r < T; r += NTH) tv[r][r] = 0;
+    for (int r = tid; r < T; r += NTH) tv[r][r] = OB && r < nI ? (int64_t)ob_q[base + r] : 0;
     __syncthreads();
 
     const int r = tid >> 2, g = tid & 3;
@@ -123,7 +130,7 @@ __global__ __launch_bounds__(NTH) void k_tri(const TileChain *__restrict__ chain
             }
         }
         if (c < nI && g == 0) {
-            tv[r][c] = best;
+            tv[r][c] = OB ? best + (ob_hi[base + c] - ob_lo[base + r]) : best;
             sv[r][c] = base + arg;
         }
         __syncthreads();
@@ -428,13 +435,18 @@ __device__ __forceinline__ double close_step_at(int t0, const CloseRegs<G> &R, c
     return close_step<G, T0>(R, L, cc, g, pJc);
 }
 
-template <int G, class Lds>
+// OB: the optimal-BST weights (pd_all then holds zeros, so every product
+// term vanishes): a cell gains W(i, j) = ob_hi[j] - ob_lo[i] once its
+// minimum is known.  pJs then carries ob_hi of the tile's columns.
+template <int G, class Lds, bool OB>
 __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__ chains,
                                            const TileSeg *__restrict__ segs, int nseg,
                                            int64_t *__restrict__ m_all,
                                            int32_t *__restrict__ s_all,
                                            const double *__restrict__ pd_all,
-                                           const uint64_t *__restrict__ part_all)
+                                           const uint64_t *__restrict__ part_all,
+                                           const double *__restrict__ ob_hi,
+                                           const double *__restrict__ ob_lo)
 {
     constexpr int CTH = CloseShape<G>::CTH, CS = CloseShape<G>::CS;
     constexpr int CROWS = CloseShape<G>::CROWS;
@@ -468,7 +480,13 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
         R.Xrow[t] = kPad;  // until cell (r, q) is final
     }
 
-    for (int q = tid; q <= T; q += CTH) L.pJs[q] = q <= nJ ? pd[col0 + q] : 0.0;
+    if constexpr (OB) {
+        for (int q = tid; q <= T; q += CTH)
+            L.pJs[q] = q >= 1 && q <= nJ ? ob_hi[col0 + q - 1] : 0.0;
+    } else {
+        for (int q = tid; q <= T; q += CTH) L.pJs[q] = q <= nJ ? pd[col0 + q] : 0.0;
+    }
+    const double w_row = OB ? ob_lo[row0 + r] : 0.0;
     {
         double *z = &L.Xt[0][0];
         for (int idx = tid; idx < T * CSTR; idx += CTH) z[idx] = 0.0;
@@ -559,7 +577,8 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
             const double xbulk = L.Xt[cc][r];
             const double best = close_step_at<G, 0>((h * CROWS) / G, R, L, cc, g, pJc);
             const double fin = fmin(best, xbulk);
-            const double cost = floor(fin * inv_scale);
+            const double base = floor(fin * inv_scale);
+            const double cost = OB ? base + (pJc - w_row) : base;
             const double xv = cost * scale;
             if (c >= 0 && c < nJ) {
 #pragma unroll
@@ -567,7 +586,7 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
                     if (t * G + g == c) R.Xrow[t] = xv;
                 if (g == 0) {
                     L.Xt[c][r] = xv;
-                    const int kl = (int)fma(-cost, scale, fin);
+                    const int kl = (int)fma(-base, scale, fin);
                     if (kl != T - 1) L.Ks[r][c] = kl < T - 1 ? row0 + kl : col0 + (kl - T);
                 }
             }
@@ -600,7 +619,8 @@ __global__ __launch_bounds__(CloseShape<CG_LONE>::CTH) void k_close(
     const uint64_t *__restrict__ part_all)
 {
     __shared__ CloseLdsFull L;
-    close_tile<CG_LONE>(L, chains, segs, nseg, m_all, s_all, pd_all, part_all);
+    close_tile<CG_LONE, CloseLdsFull, false>(L, chains, segs, nseg, m_all, s_all, pd_all,
+                                             part_all, nullptr, nullptr);
 }
 
 // Two tiles per CU (many chains: closure throughput matters).
@@ -610,7 +630,31 @@ __global__ __launch_bounds__(CloseShape<CG_PAIR>::CTH) void k_close_pair(
     const uint64_t *__restrict__ part_all)
 {
     __shared__ CloseLdsPacked L;
-    close_tile<CG_PAIR>(L, chains, segs, nseg, m_all, s_all, pd_all, part_all);
+    close_tile<CG_PAIR, CloseLdsPacked, false>(L, chains, segs, nseg, m_all, s_all, pd_all,
+                                               part_all, nullptr, nullptr);
+}
+
+// The same closures with the optimal-BST weights.
+__global__ __launch_bounds__(CloseShape<CG_LONE>::CTH) void k_close_ob(
+    const TileChain *__restrict__ chains, const TileSeg *__restrict__ segs, int nseg,
+    int64_t *__restrict__ m_all, int32_t *__restrict__ s_all, const double *__restrict__ pd_all,
+    const uint64_t *__restrict__ part_all, const double *__restrict__ ob_hi,
+    const double *__restrict__ ob_lo)
+{
+    __shared__ CloseLdsFull L;
+    close_tile<CG_LONE, CloseLdsFull, true>(L, chains, segs, nseg, m_all, s_all, pd_all,
+                                            part_all, ob_hi, ob_lo);
+}
+
+__global__ __launch_bounds__(CloseShape<CG_PAIR>::CTH) void k_close_pair_ob(
+    const TileChain *__restrict__ chains, const TileSeg *__restrict__ segs, int nseg,
+    int64_t *__restrict__ m_all, int32_t *__restrict__ s_all, const double *__restrict__ pd_all,
+    const uint64_t *__restrict__ part_all, const double *__restrict__ ob_hi,
+    const double *__restrict__ ob_lo)
+{
+    __shared__ CloseLdsPacked L;
+    close_tile<CG_PAIR, CloseLdsPacked, true>(L, chains, segs, nseg, m_all, s_all, pd_all,
+                                              part_all, ob_hi, ob_lo);
 }
 
 static_assert(2 * sizeof(CloseLdsPacked) <= 163840, "two paired closures per CU");
@@ -1029,7 +1073,8 @@ void plan_lockstep(TiledPlan &plan, const std::vector<int> &ids)
 }
 
 mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double *pd,
-                          int64_t *m_all, int32_t *s_all, uint64_t *part_ext, hipStream_t stream)
+                          int64_t *m_all, int32_t *s_all, uint64_t *part_ext, hipStream_t stream,
+                          const ObstWeights *ob)
 {
     if (plan.launches.empty()) return MCM_OK;
     // One device block: chain table, then segment table.
@@ -1086,8 +1131,12 @@ mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double 
         const TileSeg *sg = segs + L.seg_begin;
         if (L.kind == TK_TRI) {
             ProfileScope ps(KC_SETUP, q, L.evals);
-            hipLaunchKernelGGL(k_tri, dim3(L.blocks), dim3(NTH), 0, q, chains, sg, L.nseg, p,
-                               m_all, s_all);
+            if (ob)
+                hipLaunchKernelGGL(k_tri<true>, dim3(L.blocks), dim3(NTH), 0, q, chains, sg,
+                                   L.nseg, p, m_all, s_all, ob->hi, ob->lo, ob->q);
+            else
+                hipLaunchKernelGGL(k_tri<false>, dim3(L.blocks), dim3(NTH), 0, q, chains, sg,
+                                   L.nseg, p, m_all, s_all, nullptr, nullptr, nullptr);
             e = hipGetLastError();
         } else if (L.kind == TK_BULK) {
             ProfileScope ps(KC_BULK, q, L.evals);
@@ -1098,7 +1147,16 @@ mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double 
             ProfileScope ps(KC_CLOSE, q, L.evals);
             // Paired closures (two per CU, each somewhat slower) only when
             // the launch has more tiles than the device has CUs.
-            if (plan.lone || L.blocks <= cus)
+            const bool lone = plan.lone || L.blocks <= cus;
+            if (ob && lone)
+                hipLaunchKernelGGL(k_close_ob, dim3(L.blocks), dim3(CloseShape<CG_LONE>::CTH),
+                                   kCloseExtraLds, q, chains, sg, L.nseg, m_all, s_all, pd, part,
+                                   ob->hid, ob->lod);
+            else if (ob)
+                hipLaunchKernelGGL(k_close_pair_ob, dim3(L.blocks),
+                                   dim3(CloseShape<CG_PAIR>::CTH), 0, q, chains, sg, L.nseg,
+                                   m_all, s_all, pd, part, ob->hid, ob->lod);
+            else if (lone)
                 hipLaunchKernelGGL(k_close, dim3(L.blocks), dim3(CloseShape<CG_LONE>::CTH),
                                    kCloseExtraLds, q, chains, sg, L.nseg, m_all, s_all, pd, part);
             else
@@ -1137,7 +1195,20 @@ mcm_status run_tiled(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int
     plan.slots_per_cu = bulk_blocks_per_cu();
     const int c = plan_add_chain(plan, ci, 0, 0, 0, 0);
     plan_lockstep(plan, {c});
-    return run_tiled_plan(plan, dc.p, dc.pd, m, s, nullptr, stream);
+    return run_tiled_plan(plan, dc.p, dc.pd, m, s, nullptr, stream, nullptr);
+}
+
+mcm_status run_tiled_obst(const ChainInfo &ci, const int32_t *p_zero, const double *pd_zero,
+                          const ObstWeights &ob, int64_t *e, int32_t *split, hipStream_t stream)
+{
+    if (!tiled_accepts(ci)) return MCM_ERR_UNSUPPORTED;
+    TiledPlan plan;
+    plan.lone = true;
+    plan.cus = device_cus();
+    plan.slots_per_cu = bulk_blocks_per_cu();
+    const int c = plan_add_chain(plan, ci, 0, 0, 0, 0);
+    plan_lockstep(plan, {c});
+    return run_tiled_plan(plan, p_zero, pd_zero, e, split, nullptr, stream, &ob);
 }
 
 }  // namespace mcm

@@ -180,10 +180,27 @@ struct SdpPlan {
 
 mcm_status run_sdp(const SdpPlan &plan, int op, int32_t *st, hipStream_t stream);
 
+// Optimal-BST weights for the tiled kernels (device pointers, one chain of
+// L = n+1 gaps): W(i, j) = hi[j] - lo[i] (int64 and exact fp64 copies) and
+// the gap weights q on the diagonal.
+struct ObstWeights {
+    const int64_t *hi = nullptr, *lo = nullptr;
+    const double *hid = nullptr, *lod = nullptr;
+    const int32_t *q = nullptr;
+};
+
+// The optimal BST on the tiled kernels: p_zero / pd_zero hold L+1 zeros (no
+// product term); split receives the split k of each cell (-1 at and below
+// the diagonal).
+mcm_status run_tiled_obst(const ChainInfo &ci, const int32_t *p_zero, const double *pd_zero,
+                          const ObstWeights &ob, int64_t *e, int32_t *split, hipStream_t stream);
+
 // Optimal binary search tree over L = n+1 gaps (k_interval.hip): q (L
 // int32), W(a, b) = hi_w[b] - lo_w[a]; e and root are L x L.
 mcm_status run_obst(const int32_t *q, const int64_t *hi_w, const int64_t *lo_w, int32_t L,
                     int64_t *e, int32_t *root, hipStream_t stream);
+// Splits (k) to root keys (k + 1) in place; -1 entries stay.
+mcm_status run_obst_root(int32_t *root, int32_t L, hipStream_t stream);
 
 // Wavefront path (int64, any valid input).
 mcm_status run_wavefront(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int32_t *s,
@@ -250,6 +267,7 @@ void plan_lockstep(TiledPlan &plan, const std::vector<int> &ids);
 // plan.part_elems allocated here.
 mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double *pd,
                           int64_t *m_all, int32_t *s_all, uint64_t *part_ext,
-                          hipStream_t stream);
+                          hipStream_t stream,
+                          const ObstWeights *ob = nullptr);
 
 }  // namespace mcm

@@ -25,10 +25,10 @@ def _gpu():
     binding.load()
 
 
-def _solve(p, q):
+def _solve(p, q, algo="auto"):
     import torch
-    _say(f"[gpu] obst n={len(p)}")
-    e, r = binding.obst_solve(p, q)
+    _say(f"[gpu] obst n={len(p)} algo={algo}")
+    e, r = binding.obst_solve(p, q, algo=algo)
     torch.cuda.synchronize()
     return e.cpu().numpy(), r.cpu().numpy()
 
@@ -38,25 +38,46 @@ def test_textbook_example():
     assert e[0][5] == 275 and r[0][5] == 2
 
 
-@pytest.mark.parametrize("n,hi,seed", [(0, 9, 0), (1, 9, 1), (2, 1, 2), (7, 3, 3), (64, 1000, 4),
-                                       (65, 0, 5), (130, 50, 6), (160, 100000, 7)])
-def test_against_oracle(n, hi, seed):
+@pytest.mark.parametrize("algo", ["wavefront", "tiled"])
+@pytest.mark.parametrize("n,hi,seed", [(1, 9, 1), (2, 1, 2), (7, 3, 3), (63, 7, 8), (64, 1000, 4),
+                                       (65, 0, 5), (130, 50, 6), (160, 100000, 7), (200, 2, 9)])
+def test_against_oracle(n, hi, seed, algo):
     rng = np.random.default_rng(seed)
     p = rng.integers(0, hi + 1, size=n).astype(np.int32)
     q = rng.integers(0, hi + 1, size=n + 1).astype(np.int32)
-    e, r = _solve(p, q)
+    e, r = _solve(p, q, algo)
     oe, orr = interval.obst_tables(p, q)
     assert np.array_equal(e, oe) and np.array_equal(r, orr)
 
 
-def test_large_sampled_recurrence():
+def test_no_keys():
+    e, r = _solve(np.zeros(0, dtype=np.int32), np.array([5], dtype=np.int32))
+    assert e.tolist() == [[5]] and r.tolist() == [[-1]]
+
+
+def test_tiled_range_and_fallback():
+    # Weights too large for the fp64 keys: the tiled path refuses, AUTO
+    # takes the int64 diagonal launches, and both agree with the oracle.
+    n = 90
+    rng = np.random.default_rng(12)
+    p = rng.integers((1 << 31) - 1000, (1 << 31) - 1, size=n).astype(np.int32)
+    q = rng.integers((1 << 31) - 1000, (1 << 31) - 1, size=n + 1).astype(np.int32)
+    with pytest.raises(binding.MCMError):
+        _solve(p, q, "tiled")
+    e, r = _solve(p, q, "auto")
+    oe, orr = interval.obst_tables(p, q)
+    assert np.array_equal(e, oe) and np.array_equal(r, orr)
+
+
+@pytest.mark.parametrize("algo", ["wavefront", "tiled"])
+def test_large_sampled_recurrence(algo):
     # n = 3000: every sampled cell must satisfy the recurrence over the
     # table's own entries, with the smallest root; the diagonal holds q.
     n = 3000
     rng = np.random.default_rng(9)
     p = rng.integers(0, 1 << 20, size=n).astype(np.int64)
     q = rng.integers(0, 1 << 20, size=n + 1).astype(np.int64)
-    e, r = _solve(p.astype(np.int32), q.astype(np.int32))
+    e, r = _solve(p.astype(np.int32), q.astype(np.int32), algo)
     assert np.array_equal(np.diag(e), q) and np.array_equal(e, e.T)
     cq = np.concatenate([[0], np.cumsum(q)])
     cp = np.concatenate([[0], np.cumsum(p)])
