@@ -55,6 +55,28 @@ __device__ __forceinline__ void sdp_atomic(int32_t *p, int32_t v)
     else atomicAdd(p, v);
 }
 
+// dst[x] = src[x] for x < len, NT threads, eight loads in flight per thread
+// before the LDS writes (one load at a time would wait out the memory
+// latency on every element).
+template <int NT>
+__device__ __forceinline__ void stage_lds(int32_t *dst, const int32_t *__restrict__ src, int len,
+                                          int tid)
+{
+    for (int base = 0; base < len; base += NT * 8) {
+        int32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int x = base + u * NT + tid;
+            v[u] = x < len ? src[x] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int x = base + u * NT + tid;
+            if (x < len) dst[x] = v[u];
+        }
+    }
+}
+
 template <int OP>
 __global__ __launch_bounds__(256) void k_sdp_fill(int32_t *__restrict__ part, int64_t count)
 {
@@ -87,8 +109,8 @@ __global__ __launch_bounds__(kFarTile) void k_sdp_far(const int32_t *__restrict_
     const int lo = t0 - amax;
     const int hi = min(t0 + kFarTile, tend) - 1 - amin;
     const int tid = threadIdx.x;
-    for (int x = tid; x < nj; x += kFarTile) offs[x] = a[ch.x + x];
-    for (int x = tid; x <= hi - lo; x += kFarTile) src[x] = st[lo + x];
+    stage_lds<kFarTile>(offs, a + ch.x, nj, tid);
+    stage_lds<kFarTile>(src, st + lo, hi - lo + 1, tid);
     __syncthreads();
     const int i = t0 + tid;
     if (i >= tend) return;
@@ -126,11 +148,10 @@ __global__ __launch_bounds__(kNearThreads) void k_sdp_near(int32_t *__restrict__
     int32_t *na = lds + 2 * B;            // kn offsets (< B), ascending
     const int tid = threadIdx.x;
     const int len = tend - t;
-    for (int x = tid; x < B; x += kNearThreads) {
-        blk[x] = x < len ? part[t + x] : sdp_identity<OP>();
-        cle[x] = cnt_le[x];
-    }
-    for (int x = tid; x < kn; x += kNearThreads) na[x] = near_a[x];
+    stage_lds<kNearThreads>(blk, part + t, len, tid);
+    for (int x = len + tid; x < B; x += kNearThreads) blk[x] = sdp_identity<OP>();
+    stage_lds<kNearThreads>(cle, cnt_le, B, tid);
+    stage_lds<kNearThreads>(na, near_a, kn, tid);
     const int lane = tid & 63;
     const uint64_t gm = tid < 64 ? seq_mask[lane] : 0;
     const uint32_t gm_lo = (uint32_t)gm, gm_hi = (uint32_t)(gm >> 32);
