@@ -243,6 +243,25 @@ def bench_obst(binding, torch, n: int = 8192, reps: int = 3):
     return out
 
 
+def bench_pipeline(binding, workloads, torch, sizes=(512, 1024)):
+    """Ablation: the paper's pipeline (Fig. 8, with stalls; one workgroup, a
+    barrier per step) against the wavefront and tiled paths, same chains
+    (dims uniform [1, 1024], seed 7)."""
+    out = {}
+    for n in sizes:
+        p = workloads.uniform_dims(n, 1, 1024, 7)
+        row = {}
+        for algo in ("pipeline", "wavefront", "tiled"):
+            m, s = binding.solve(p, algo=algo)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m, s = binding.solve(p, algo=algo)
+            torch.cuda.synchronize()
+            row[f"{algo}_ms"] = 1e3 * (time.perf_counter() - t0)
+        out[f"n{n}"] = row
+    return {"workload": "MCM chains, dims uniform [1, 1024], seed 7", "sizes": out}
+
+
 def bench_serving(binding, workloads, torch, count: int, rate: float):
     """Open-loop Poisson stream (seed 4, n log-uniform in [8, 4096], dims in
     [1, 1024]): continuous-batching server against plain FIFO solves."""
@@ -296,6 +315,8 @@ def main() -> int:
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--no-sdp", action="store_true", help="skip the S-DP section")
     ap.add_argument("--no-obst", action="store_true", help="skip the optimal-BST section")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="skip the pipeline (Fig. 8) ablation section")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-rate", type=float, default=600.0, help="Poisson arrivals per second")
     args = ap.parse_args()
@@ -405,6 +426,8 @@ def main() -> int:
         out["sdp"] = bench_sdp(binding, workloads, torch)
     if not args.no_obst:
         out["obst"] = bench_obst(binding, torch)
+    if not args.no_pipeline:
+        out["pipeline_ablation"] = bench_pipeline(binding, workloads, torch)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(out), flush=True)

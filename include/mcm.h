@@ -71,11 +71,21 @@ typedef enum mcm_status {
  *                       workgroups; a per-tile closure pass in LDS.  Exact
  *                       integers carried in fp64; accepts inputs with
  *                       (n-1) * max(p)^3 < 2^46 (else MCM_ERR_UNSUPPORTED).
+ *   MCM_ALGO_PIPELINE   the paper's pipeline (Section IV-B, Fig. 8): the
+ *                       table linearised in diagonal order, thread j folding
+ *                       split j of an element one step after thread j-1, a
+ *                       barrier per step, in one workgroup; each element
+ *                       starts once its operands are final (a stall where
+ *                       the printed schedule would read too early).  An
+ *                       ablation, far slower than the others; int64;
+ *                       n <= 1025 (else MCM_ERR_UNSUPPORTED); never chosen
+ *                       by AUTO.
  */
 typedef enum mcm_algo {
     MCM_ALGO_AUTO = 0,
     MCM_ALGO_WAVEFRONT = 1,
-    MCM_ALGO_TILED = 2
+    MCM_ALGO_TILED = 2,
+    MCM_ALGO_PIPELINE = 3
 } mcm_algo;
 
 /* Static, NUL-terminated description of a status code (never NULL). */

@@ -24,7 +24,9 @@ ERR_UNSUPPORTED = 5
 ALGO_AUTO = 0
 ALGO_WAVEFRONT = 1
 ALGO_TILED = 2
-ALGOS = {"auto": ALGO_AUTO, "wavefront": ALGO_WAVEFRONT, "tiled": ALGO_TILED}
+ALGO_PIPELINE = 3
+ALGOS = {"auto": ALGO_AUTO, "wavefront": ALGO_WAVEFRONT, "tiled": ALGO_TILED,
+         "pipeline": ALGO_PIPELINE}
 
 # Profiler kernel classes (mcm_profile_read).
 PROF_SETUP, PROF_BULK, PROF_CLOSE, PROF_WAVE, PROF_BATCH = range(5)

@@ -355,8 +355,10 @@ mcm_status check_outputs(const ChainInfo &ci, int64_t *m_out, int32_t *s_out, in
     if (m_out == nullptr || s_out == nullptr) return MCM_ERR_INVALID_ARG;
     if (((uintptr_t)m_out & 7) != 0 || ((uintptr_t)s_out & 3) != 0) return MCM_ERR_INVALID_ARG;
     if (*algo == MCM_ALGO_AUTO) *algo = tiled_accepts(ci) ? MCM_ALGO_TILED : MCM_ALGO_WAVEFRONT;
-    if (*algo != MCM_ALGO_WAVEFRONT && *algo != MCM_ALGO_TILED) return MCM_ERR_INVALID_ARG;
+    if (*algo != MCM_ALGO_WAVEFRONT && *algo != MCM_ALGO_TILED && *algo != MCM_ALGO_PIPELINE)
+        return MCM_ERR_INVALID_ARG;
     if (*algo == MCM_ALGO_TILED && !tiled_accepts(ci)) return MCM_ERR_UNSUPPORTED;
+    if (*algo == MCM_ALGO_PIPELINE && ci.n > kPipeMaxN) return MCM_ERR_UNSUPPORTED;
     return MCM_OK;
 }
 
@@ -364,6 +366,7 @@ mcm_status run_algo(const DeviceChain &dc, const ChainInfo &ci, int32_t algo, in
                     int32_t *s_out, hipStream_t stream)
 {
     if (algo == MCM_ALGO_TILED) return run_tiled(dc, ci, m_out, s_out, stream);
+    if (algo == MCM_ALGO_PIPELINE) return run_pipeline_solve(dc.p, ci.n, m_out, s_out, stream);
     return run_wavefront(dc, ci, m_out, s_out, stream);
 }
 

@@ -202,6 +202,26 @@ mcm_status run_obst(const int32_t *q, const int64_t *hi_w, const int64_t *lo_w, 
 // Splits (k) to root keys (k + 1) in place; -1 entries stay.
 mcm_status run_obst_root(int32_t *root, int32_t L, hipStream_t stream);
 
+// The pipeline of Fig. 8 with stalls (k_pipeline.hip), an ablation: one
+// workgroup, n <= 1025.  Device pointers; inv[u] = the element started at
+// step u (or -1), elem[x] = i | d << 16, st / sk the linear table.
+struct PipePlan {
+    const int32_t *inv = nullptr;
+    int64_t S = 0, steps = 0;
+    const int32_t *elem = nullptr;
+    int64_t *st = nullptr;
+    int32_t *sk = nullptr;
+};
+constexpr int32_t kPipeMaxN = 1025;
+mcm_status run_pipeline(const PipePlan &plan, const int32_t *p, int32_t n, int64_t *m,
+                        int32_t *s, hipStream_t stream);
+// Host schedule of the stalled pipeline: sigma-ordered element table (inv),
+// element codes, and the step count.
+void pipeline_schedule(int32_t n, std::vector<int32_t> &inv, std::vector<int32_t> &elem,
+                       int64_t &steps);
+mcm_status run_pipeline_solve(const int32_t *p_dev, int32_t n, int64_t *m, int32_t *s,
+                              hipStream_t stream);
+
 // Wavefront path (int64, any valid input).
 mcm_status run_wavefront(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int32_t *s,
                          hipStream_t stream);
