@@ -81,6 +81,20 @@ def host_threads() -> int:
     return max(1, n)
 
 
+def host_cpu() -> dict:
+    """Model name and logical CPU count of the host (from /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(), "threads_allowed": host_threads()}
+
+
 def cpu_baseline(p, target_s: float):
     """Time the oracle on a window p[0:L+1] of the chain, L sized so the
     run takes about target_s seconds of wall time on all host threads."""
@@ -99,15 +113,17 @@ def cpu_baseline(p, target_s: float):
     dt = time.perf_counter() - t0
     evals = (L ** 3 - L) / 6
     return {"value": evals / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "host": host_cpu(),
             "sample": f"oracle on the window of the first {L} matrices of the benchmark "
                       f"chain ({evals:.3g} split evals, {dt:.1f} s wall, OpenMP over the "
                       f"cells of each diagonal)"}
 
 
 def bench_batched(binding, workloads, torch, reps: int = 3):
-    """4096 chains (n in [16, 512], dims in [1, 256], seed 3): one
-    mcm_solve_batched call against 4096 plain per-chain solves on one stream
-    (chains already resident on the device in both cases)."""
+    """4096 chains (n in [16, 512], dims in [1, 256], seed 3): one batched
+    solve (a reusable plan, and the one-shot mcm_solve_batched) against 4096
+    plain per-chain solves on one stream (chains already resident on the
+    device for the plain solves)."""
     b = workloads.batched_4096()
     off = binding.table_offsets(b.ns)
     total = int(off[-1] + int(b.ns[-1]) ** 2)
@@ -115,13 +131,27 @@ def bench_batched(binding, workloads, torch, reps: int = 3):
     s_all = torch.empty(total, dtype=torch.int32, device="cuda")
     binding.solve_batched_into(b.ns, b.p_off, b.p_all, off, m_all, s_all)
     torch.cuda.synchronize()
-    best = None
+    oneshot = None
     for _ in range(reps):
         t0 = time.perf_counter()
         binding.solve_batched_into(b.ns, b.p_off, b.p_all, off, m_all, s_all)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        oneshot = dt if oneshot is None else min(oneshot, dt)
+    # The same batch through a plan built (and autotuned) once for its shape.
+    t0 = time.perf_counter()
+    plan = binding.Plan(b.ns, b.p_off, off, int(b.p_all.max()))
+    plan_build = time.perf_counter() - t0
+    choice = plan.autotune(b.p_all, m_all, s_all)
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.solve_into(b.p_all, m_all, s_all)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
         best = dt if best is None else min(best, dt)
+    plan.close()
     # Read back all 4096 trees (with their costs) in one launch.
     node_off = binding.node_offsets(b.ns)
     g = int(node_off[-1] + b.ns[-1] - 1)
@@ -157,9 +187,13 @@ def bench_batched(binding, workloads, torch, reps: int = 3):
             "split_evals_per_s": evals / best,
             "plain_instances_per_s": count / plain, "plain_ms": 1e3 * plain,
             "speedup_vs_plain": plain / best,
+            "oneshot_ms": 1e3 * oneshot, "plan_build_ms": 1e3 * plan_build,
+            "plan_pair_min_blocks": choice,
             "readback_ms": 1e3 * rb, "readback_costs_equal_m0n": rb_ok,
-            "note": "batched time includes the host dims upload of mcm_solve_batched; "
-                    "readback is mcm_parenthesize_batched (trees and costs of all chains)"}
+            "note": "ms: mcm_plan_solve of a plan built and autotuned once for the batch "
+                    "(host dims upload included); oneshot_ms: mcm_solve_batched, which also "
+                    "plans and uploads its launch tables; readback is "
+                    "mcm_parenthesize_batched (trees and costs of all chains)"}
 
 
 def bench_reconstruction(binding, torch, p, m, s, reps: int = 5):
@@ -357,13 +391,24 @@ def main() -> int:
         chain.solve_into(m, s, algo=algo)
     torch.cuda.synchronize()
 
-    binding.profile_enable(True)
+    # The timed steps mark only the dominant kernel's launches with events
+    # (every marked launch adds two event records to its stream).
+    dom = "bulk" if chosen == "tiled" else "wavefront"
+    dom_class = binding.PROF_BULK if dom == "bulk" else binding.PROF_WAVE
+    binding.profile_enable(True, classes=[dom_class])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         chain.solve_into(m, s, algo=algo)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    d = binding.profile_read(dom_class)
+    binding.profile_enable(False)
+
+    # Per-class kernel time from one more solve with every class marked.
+    binding.profile_enable(True)
+    chain.solve_into(m, s, algo=algo)
+    torch.cuda.synchronize()
     prof = {name: binding.profile_read(c) for c, name in
             enumerate(["setup", "bulk", "close", "wavefront", "batched"])}
     binding.profile_enable(False)
@@ -372,9 +417,6 @@ def main() -> int:
     evals = (n ** 3 - n) / 6
     value = evals * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
-
-    dom = "bulk" if chosen == "tiled" else "wavefront"
-    d = prof[dom]
     avg_s = d["ms"] / 1e3 / max(1, d["launches"])
     evals_per_launch = d["split_evals"] / max(1, d["launches"])
     achieved = evals_per_launch * OPS_PER_EVAL / avg_s if avg_s > 0 else 0.0
@@ -408,7 +450,7 @@ def main() -> int:
         "config": {"workload": args.workload, "n": n, "dims": desc, "algo": chosen,
                    "exact_integer": True, "parallelism": "single GPU"},
         "roofline": roofline,
-        "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in prof.items()},
+        "kernels_ms_per_step": {k: round(v["ms"], 4) for k, v in prof.items()},
     }
     rec = bench_reconstruction(binding, torch, p, m, s)
     rec["solve_fraction"] = round(rec["tree_cost_text_ms"] / ms_per_step, 4)

@@ -149,6 +149,49 @@ mcm_status mcm_solve_batched(int32_t count, const int32_t *n, const int64_t *p_o
                              int32_t *s_all, hipStream_t stream);
 
 /*
+ * Reusable batched plan: the schedule of mcm_solve_batched (every chain's
+ * tile-diagonals advanced together, Section IV-A's diagonal order per
+ * chain) built once for a fixed batch shape, its launch tables kept in
+ * device memory, then solved for any dims that respect the shape.
+ *   mcm_plan_create   count, n, p_off and tab_off as in mcm_solve_batched
+ *                     (host, read before return); max_dim >= 1 bounds every
+ *                     dimension the plan will be solved with (the tiled
+ *                     path's exact key width is sized for it, so a chain
+ *                     whose (n-1) * max_dim^3 exceeds that range takes the
+ *                     int64 wavefront).  Validates the shape (INVALID_ARG,
+ *                     OVERFLOW as mcm_check_chain with every dim = max_dim)
+ *                     before any HIP call, then allocates and copies the
+ *                     tables synchronously on the current device.  *out
+ *                     receives a handle owned by the caller.
+ *   mcm_plan_solve    enqueues one batched solve on `stream` (current device
+ *                     = the plan's): p_all (host) holds every chain's dims at
+ *                     its p_off; m_all / s_all (device, caller-owned) receive
+ *                     the tables at tab_off, same contract as
+ *                     mcm_solve_batched.  A dim outside [1, max_dim] returns
+ *                     MCM_ERR_INVALID_ARG before anything is enqueued.  The
+ *                     plan is read only: solves of one plan may run on
+ *                     several streams at once with distinct outputs.
+ *   mcm_plan_autotune times the plan's closure shape (paired closures, two
+ *                     per compute unit, for launches above a tile-count
+ *                     threshold) at four thresholds on the given inputs and
+ *                     keeps the fastest; writes m_all / s_all as a solve
+ *                     does and synchronises `stream`.  *choice (may be NULL)
+ *                     receives the threshold.  Must not run concurrently
+ *                     with solves of the same plan.
+ *   mcm_plan_destroy  frees the plan (its device tables with hipFree, so
+ *                     after the device has finished with them); NULL is
+ *                     ignored.
+ */
+typedef struct mcm_plan mcm_plan;
+mcm_status mcm_plan_create(int32_t count, const int32_t *n, const int64_t *p_off,
+                           const int64_t *tab_off, int32_t max_dim, mcm_plan **out);
+mcm_status mcm_plan_solve(const mcm_plan *plan, const int32_t *p_all, int64_t *m_all,
+                          int32_t *s_all, hipStream_t stream);
+mcm_status mcm_plan_autotune(mcm_plan *plan, const int32_t *p_all, int64_t *m_all,
+                             int32_t *s_all, hipStream_t stream, int32_t *choice);
+void mcm_plan_destroy(mcm_plan *plan);
+
+/*
  * Device-resident chain: validated once, dimensions copied to device
  * memory, then solved any number of times without touching the host p.
  *   mcm_chain_create  validates p (host, n+1 entries, read before return)
@@ -360,6 +403,10 @@ double mcm_clock_now(void);
  * (the algorithmic count, not counting padding).
  */
 void mcm_profile_enable(int32_t on);
+/* Times only the classes whose bit is set (bit c: class c); 0 disables.
+ * Each timed launch adds two event records to its stream, so a caller that
+ * times one kernel class can leave the others unmarked. */
+void mcm_profile_enable_mask(uint32_t mask);
 mcm_status mcm_profile_read(int32_t kernel_class, double *total_ms, int64_t *launches,
                             double *split_evals);
 

@@ -34,10 +34,11 @@ PROF_SETUP, PROF_BULK, PROF_CLOSE, PROF_WAVE, PROF_BATCH = range(5)
 # Every symbol include/mcm.h declares.
 EXPORTED = (
     "mcm_status_string", "mcm_version", "mcm_check_chain", "mcm_select_algo",
-    "mcm_solve", "mcm_solve_algo", "mcm_solve_batched", "mcm_chain_create", "mcm_chain_solve", "mcm_chain_n",
+    "mcm_solve", "mcm_solve_algo", "mcm_solve_batched", "mcm_plan_create", "mcm_plan_solve",
+    "mcm_plan_autotune", "mcm_plan_destroy", "mcm_chain_create", "mcm_chain_solve", "mcm_chain_n",
     "mcm_chain_destroy", "mcm_server_create", "mcm_server_submit", "mcm_server_poll",
     "mcm_server_release", "mcm_server_request_bytes", "mcm_server_stats", "mcm_server_destroy", "mcm_clock_now",
-    "mcm_profile_enable", "mcm_profile_read", "mcm_parens_length", "mcm_parenthesize",
+    "mcm_profile_enable", "mcm_profile_enable_mask", "mcm_profile_read", "mcm_parens_length", "mcm_parenthesize",
     "mcm_parenthesize_batched", "mcm_sdp_solve", "mcm_obst_solve",
     "mcm_obst_solve_algo",
 )
@@ -103,6 +104,16 @@ def load() -> ctypes.CDLL:
             lib.mcm_chain_n.restype = ctypes.c_int32
             lib.mcm_chain_destroy.argtypes = [vp, vp]
             lib.mcm_chain_destroy.restype = None
+            i64p = ctypes.POINTER(ctypes.c_int64)
+            lib.mcm_plan_create.argtypes = [ctypes.c_int32, i32p, i64p, i64p, ctypes.c_int32,
+                                            ctypes.POINTER(vp)]
+            lib.mcm_plan_create.restype = ctypes.c_int
+            lib.mcm_plan_solve.argtypes = [vp, i32p, vp, vp, vp]
+            lib.mcm_plan_solve.restype = ctypes.c_int
+            lib.mcm_plan_autotune.argtypes = [vp, i32p, vp, vp, vp, ctypes.POINTER(ctypes.c_int32)]
+            lib.mcm_plan_autotune.restype = ctypes.c_int
+            lib.mcm_plan_destroy.argtypes = [vp]
+            lib.mcm_plan_destroy.restype = None
             lib.mcm_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, vp,
                                               ctypes.POINTER(vp)]
             lib.mcm_server_create.restype = ctypes.c_int
@@ -123,6 +134,8 @@ def load() -> ctypes.CDLL:
             lib.mcm_clock_now.restype = ctypes.c_double
             lib.mcm_profile_enable.argtypes = [ctypes.c_int32]
             lib.mcm_profile_enable.restype = None
+            lib.mcm_profile_enable_mask.argtypes = [ctypes.c_uint32]
+            lib.mcm_profile_enable_mask.restype = None
             lib.mcm_profile_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_int64),
                                              ctypes.POINTER(ctypes.c_double)]
@@ -444,6 +457,74 @@ class Chain:
             self._h = None
 
 
+class Plan:
+    """A batched plan (mcm_plan_create) for a fixed batch shape: chain b has
+    ns[b] matrices, dims at p_all[p_off[b] : p_off[b] + ns[b] + 1], tables at
+    element offset tab_off[b]; every dim at most max_dim.  Solve it with
+    :meth:`solve_into` for any dims of that shape."""
+
+    def __init__(self, ns, p_off, tab_off, max_dim: int):
+        self.ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
+        self.p_off = np.ascontiguousarray(np.asarray(p_off, dtype=np.int64))
+        self.tab_off = np.ascontiguousarray(np.asarray(tab_off, dtype=np.int64))
+        if not (self.p_off.size == self.ns.size and self.tab_off.size == self.ns.size):
+            raise ValueError("ns, p_off and tab_off must have one entry per chain")
+        count = self.ns.size
+        self.p_len = int(np.max(self.p_off + self.ns + 1)) if count else 0
+        self.need = int(np.max(self.tab_off + self.ns.astype(np.int64) ** 2)) if count else 0
+        i64 = ctypes.POINTER(ctypes.c_int64)
+        h = ctypes.c_void_p()
+        st = load().mcm_plan_create(count, _p_ptr(self.ns), self.p_off.ctypes.data_as(i64),
+                                    self.tab_off.ctypes.data_as(i64), int(max_dim),
+                                    ctypes.byref(h))
+        if st != OK:
+            raise MCMError(st, "mcm_plan_create")
+        self._h = h
+
+    def _args(self, p_all, m_all, s_all):
+        import torch
+        p_all = np.ascontiguousarray(np.asarray(p_all, dtype=np.int32))
+        if p_all.size < self.p_len:
+            raise ValueError("p_all too short for the plan's offsets")
+        if not (m_all.is_cuda and s_all.is_cuda and m_all.dtype == torch.int64 and
+                s_all.dtype == torch.int32 and m_all.is_contiguous() and s_all.is_contiguous()):
+            raise TypeError("m_all / s_all must be contiguous CUDA int64 / int32 tensors")
+        if m_all.numel() < self.need or s_all.numel() < self.need:
+            raise ValueError("m_all / s_all too small for the plan's table offsets")
+        return p_all
+
+    def solve_into(self, p_all, m_all, s_all, stream=None) -> None:
+        p_all = self._args(p_all, m_all, s_all)
+        st = load().mcm_plan_solve(self._h, _p_ptr(p_all), ctypes.c_void_p(m_all.data_ptr()),
+                                   ctypes.c_void_p(s_all.data_ptr()),
+                                   ctypes.c_void_p(_stream_handle(stream)))
+        if st != OK:
+            raise MCMError(st, "mcm_plan_solve")
+
+    def autotune(self, p_all, m_all, s_all, stream=None) -> int:
+        """Time the closure-shape thresholds; returns the one kept."""
+        p_all = self._args(p_all, m_all, s_all)
+        choice = ctypes.c_int32(0)
+        st = load().mcm_plan_autotune(self._h, _p_ptr(p_all), ctypes.c_void_p(m_all.data_ptr()),
+                                      ctypes.c_void_p(s_all.data_ptr()),
+                                      ctypes.c_void_p(_stream_handle(stream)),
+                                      ctypes.byref(choice))
+        if st != OK:
+            raise MCMError(st, "mcm_plan_autotune")
+        return int(choice.value)
+
+    def close(self) -> None:
+        if self._h:
+            load().mcm_plan_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 def server_request_bytes(p) -> int:
     """Arena bytes the server holds for a request of chain p (0 if invalid)."""
     a = _dims(p)
@@ -535,8 +616,15 @@ class Server:
         self.close()
 
 
-def profile_enable(on: bool = True) -> None:
-    load().mcm_profile_enable(1 if on else 0)
+def profile_enable(on: bool = True, classes=None) -> None:
+    """Time every kernel class (or only those listed in `classes`)."""
+    if classes is None:
+        load().mcm_profile_enable(1 if on else 0)
+    else:
+        mask = 0
+        for c in classes:
+            mask |= 1 << int(c)
+        load().mcm_profile_enable_mask(mask if on else 0)
 
 
 def profile_read(kernel_class: int) -> dict:

@@ -73,8 +73,12 @@ __device__ __forceinline__ int find_seg(const TileSeg *__restrict__ seg, int nse
 
 // ------------------------------------------------------------------------
 // Diagonal tiles (I, I): every split of a cell inside the tile uses two
-// cells of the same tile.  Local diagonals dd = 1..nI-1 in order; four
-// lanes per cell, lexicographic (cost, k) reduction.  int64 arithmetic.
+// cells of the same tile.  Local diagonals dd = 1..nI-1 in order.  The
+// nI - dd cells of diagonal dd share the 256 lanes: L lanes per cell, L the
+// largest power of two in [4, 64] with cells * L <= 256, so a cell's lanes
+// lie in one wave and the longest scan is about 4 splits per lane.  Each
+// lane keeps a (cost, k) minimum over its splits; a shuffle tree over the L
+// lanes takes the lexicographic minimum.  int64 arithmetic.
 // ------------------------------------------------------------------------
 // OB: the optimal-BST weights (one chain; p_all then holds zeros): the
 // diagonal holds the gap weights q and every cell gains W(i, j) = hi[j] -
@@ -90,7 +94,7 @@ __global__ __launch_bounds__(NTH) void k_tri(const TileChain *__restrict__ chain
                                              const int32_t *__restrict__ ob_q)
 {
     __shared__ int64_t tv[T][T + 1];
-    __shared__ int32_t sv[T][T + 1];
+    __shared__ uint8_t sv[T][T + 4];  // local split (0..T-2) of cell (r, c), r < c
     __shared__ int64_t ps[T + 1];
     const int tid = threadIdx.x;
     const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
@@ -105,14 +109,18 @@ __global__ __launch_bounds__(NTH) void k_tri(const TileChain *__restrict__ chain
     for (int r = tid; r < T; r += NTH) tv[r][r] = OB && r < nI ? (int64_t)ob_q[base + r] : 0;
     __syncthreads();
 
-    const int r = tid >> 2, g = tid & 3;
     for (int dd = 1; dd < nI; ++dd) {
+        const int cells = nI - dd;
+        int lg = 2;  // log2 L, uniform across the workgroup
+        while (lg < 6 && (cells << (lg + 1)) <= NTH) ++lg;
+        const int L = 1 << lg;
+        const int r = tid >> lg, g = tid & (L - 1);
         const int c = r + dd;
         int64_t best = INT64_MAX;
         int32_t arg = INT32_MAX;
-        if (c < nI) {
+        if (r < cells) {
             const int64_t prc = ps[r] * ps[c + 1];
-            for (int kl = r + g; kl < c; kl += 4) {
+            for (int kl = r + g; kl < c; kl += L) {
                 const int64_t v = tv[r][kl] + tv[kl + 1][c] + prc * ps[kl + 1];
                 if (v < best) {
                     best = v;
@@ -120,18 +128,18 @@ __global__ __launch_bounds__(NTH) void k_tri(const TileChain *__restrict__ chain
                 }
             }
         }
-#pragma unroll
-        for (int off = 1; off < 4; off <<= 1) {
-            const int64_t ov = __shfl_xor(best, off, 4);
-            const int32_t oa = __shfl_xor(arg, off, 4);
+        // xor partners stay inside the L-aligned lane group of the cell.
+        for (int off = 1; off < L; off <<= 1) {
+            const int64_t ov = __shfl_xor(best, off, 64);
+            const int32_t oa = __shfl_xor(arg, off, 64);
             if (ov < best || (ov == best && oa < arg)) {
                 best = ov;
                 arg = oa;
             }
         }
-        if (c < nI && g == 0) {
+        if (r < cells && g == 0) {
             tv[r][c] = OB ? best + (ob_hi[base + c] - ob_lo[base + r]) : best;
-            sv[r][c] = base + arg;
+            sv[r][c] = (uint8_t)arg;
         }
         __syncthreads();
     }
@@ -141,7 +149,7 @@ __global__ __launch_bounds__(NTH) void k_tri(const TileChain *__restrict__ chain
         if (rr < nI && cc < nI) {
             const size_t o = (size_t)(base + rr) * n + base + cc;
             m[o] = rr <= cc ? tv[rr][cc] : tv[cc][rr];
-            s[o] = rr < cc ? sv[rr][cc] : -1;
+            s[o] = rr < cc ? base + (int32_t)sv[rr][cc] : -1;
         }
     }
 }
@@ -1072,31 +1080,53 @@ void plan_lockstep(TiledPlan &plan, const std::vector<int> &ids)
     }
 }
 
+size_t plan_tables_bytes(const TiledPlan &plan, size_t *seg_offset)
+{
+    const size_t cbytes = plan.chains.size() * sizeof(TileChain);
+    const size_t soff = (cbytes + 255) / 256 * 256;
+    if (seg_offset) *seg_offset = soff;
+    return soff + plan.segs.size() * sizeof(TileSeg);
+}
+
+void plan_tables_write(const TiledPlan &plan, char *dst)
+{
+    size_t soff = 0;
+    plan_tables_bytes(plan, &soff);
+    memcpy(dst, plan.chains.data(), plan.chains.size() * sizeof(TileChain));
+    memcpy(dst + soff, plan.segs.data(), plan.segs.size() * sizeof(TileSeg));
+}
+
 mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double *pd,
                           int64_t *m_all, int32_t *s_all, uint64_t *part_ext, hipStream_t stream,
                           const ObstWeights *ob)
 {
     if (plan.launches.empty()) return MCM_OK;
     // One device block: chain table, then segment table.
-    const size_t cbytes = plan.chains.size() * sizeof(TileChain);
-    const size_t sbytes = plan.segs.size() * sizeof(TileSeg);
-    const size_t soff = (cbytes + 255) / 256 * 256;
+    size_t soff = 0;
+    const size_t bytes = plan_tables_bytes(plan, &soff);
     void *tables = nullptr;
-    mcm_status st = upload_blob(stream, &tables, soff + sbytes, [&](char *dst) {
-        memcpy(dst, plan.chains.data(), cbytes);
-        memcpy(dst + soff, plan.segs.data(), sbytes);
-    });
+    mcm_status st =
+        upload_blob(stream, &tables, bytes, [&](char *dst) { plan_tables_write(plan, dst); });
     if (st != MCM_OK) return st;
-    const TileChain *chains = (const TileChain *)tables;
-    const TileSeg *segs = (const TileSeg *)((const char *)tables + soff);
+    st = exec_tiled_plan(plan, (const TileChain *)tables,
+                         (const TileSeg *)((const char *)tables + soff), p, pd, m_all, s_all,
+                         part_ext, stream, ob);
+    ws_free(tables, stream);
+    return st;
+}
+
+mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const TileSeg *segs,
+                           const int32_t *p, const double *pd, int64_t *m_all, int32_t *s_all,
+                           uint64_t *part_ext, hipStream_t stream, const ObstWeights *ob)
+{
+    if (plan.launches.empty()) return MCM_OK;
+    mcm_status st = MCM_OK;
     uint64_t *part = part_ext;
     uint64_t *part_own = nullptr;
     if (!part && plan.part_elems) {
         if (ws_alloc((void **)&part_own, plan.part_elems * sizeof(uint64_t), stream) !=
-            hipSuccess) {
-            ws_free(tables, stream);
+            hipSuccess)
             return MCM_ERR_NO_MEMORY;
-        }
         part = part_own;
     }
     int nrec = 0;
@@ -1146,8 +1176,10 @@ mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double 
         } else if (L.kind == TK_CLOSE) {
             ProfileScope ps(KC_CLOSE, q, L.evals);
             // Paired closures (two per CU, each somewhat slower) only when
-            // the launch has more tiles than the device has CUs.
-            const bool lone = plan.lone || L.blocks <= cus;
+            // the launch has more tiles than the device has CUs (or than
+            // the plan's tuned threshold).
+            const int pair_min = plan.pair_min_blocks > 0 ? plan.pair_min_blocks : cus;
+            const bool lone = plan.lone || L.blocks <= pair_min;
             if (ob && lone)
                 hipLaunchKernelGGL(k_close_ob, dim3(L.blocks), dim3(CloseShape<CG_LONE>::CTH),
                                    kCloseExtraLds, q, chains, sg, L.nseg, m_all, s_all, pd, part,
@@ -1181,7 +1213,6 @@ mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double 
     }
     if (aux) release_streams(ss);
     if (part_own) ws_free(part_own, stream);
-    ws_free(tables, stream);
     return st;
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string.h>
@@ -26,6 +27,12 @@ mcm_status check_chain(const int32_t *p, int32_t n, ChainInfo *ci)
         pmax = p[t] > pmax ? p[t] : pmax;
     }
     if (pmin < 1) return MCM_ERR_INVALID_ARG;
+    return chain_bound(n, pmax, ci);
+}
+
+mcm_status chain_bound(int32_t n, int32_t pmax, ChainInfo *ci)
+{
+    if (n < 1 || pmax < 1) return MCM_ERR_INVALID_ARG;
     unsigned __int128 bound = (unsigned __int128)(uint64_t)pmax * (uint64_t)pmax;
     bound *= (uint64_t)pmax;
     bound *= (uint64_t)(n - 1);
@@ -120,18 +127,40 @@ struct ProfRecord {
     hipEvent_t start, stop;
     double evals;
 };
-std::atomic<int> g_prof_on{0};
+std::atomic<uint32_t> g_prof_mask{0};  // bit c: kernel class c is timed
 std::mutex g_prof_mu;
 std::vector<ProfRecord> g_prof_pending;
+std::vector<hipEvent_t> g_prof_free;  // recycled events (creation is a host cost per launch)
 double g_prof_ms[KC_COUNT];
 int64_t g_prof_launches[KC_COUNT];
 double g_prof_evals[KC_COUNT];
 
+hipEvent_t prof_event_take()
+{
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (!g_prof_free.empty()) {
+            hipEvent_t e = g_prof_free.back();
+            g_prof_free.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+void prof_event_give_locked(hipEvent_t e)
+{
+    if (e) g_prof_free.push_back(e);
+}
+
 void prof_clear_locked()
 {
+    // Pending events may still be in flight: wait for them before reuse.
     for (auto &r : g_prof_pending) {
-        (void)hipEventDestroy(r.start);
-        (void)hipEventDestroy(r.stop);
+        (void)hipEventSynchronize(r.stop);
+        prof_event_give_locked(r.start);
+        prof_event_give_locked(r.stop);
     }
     g_prof_pending.clear();
     for (int c = 0; c < KC_COUNT; ++c) {
@@ -151,8 +180,8 @@ void prof_drain_locked()
             g_prof_launches[r.cls] += 1;
             g_prof_evals[r.cls] += r.evals;
         }
-        (void)hipEventDestroy(r.start);
-        (void)hipEventDestroy(r.stop);
+        prof_event_give_locked(r.start);
+        prof_event_give_locked(r.stop);
     }
     g_prof_pending.clear();
 }
@@ -290,13 +319,11 @@ void ws_free(void *ptr, hipStream_t stream)
 ProfileScope::ProfileScope(int cls, hipStream_t stream, double evals)
     : cls_(cls), stream_(stream), evals_(evals)
 {
-    if (!g_prof_on.load(std::memory_order_relaxed)) return;
-    if (hipEventCreate(&start_) != hipSuccess) {
-        start_ = nullptr;
-        return;
-    }
-    if (hipEventRecord(start_, stream_) != hipSuccess) {
-        (void)hipEventDestroy(start_);
+    if (!((g_prof_mask.load(std::memory_order_relaxed) >> cls) & 1u)) return;
+    start_ = prof_event_take();
+    if (start_ && hipEventRecord(start_, stream_) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        prof_event_give_locked(start_);
         start_ = nullptr;
     }
 }
@@ -304,13 +331,14 @@ ProfileScope::ProfileScope(int cls, hipStream_t stream, double evals)
 ProfileScope::~ProfileScope()
 {
     if (!start_) return;
-    hipEvent_t stop = nullptr;
-    if (hipEventCreate(&stop) != hipSuccess || hipEventRecord(stop, stream_) != hipSuccess) {
-        if (stop) (void)hipEventDestroy(stop);
-        (void)hipEventDestroy(start_);
+    hipEvent_t stop = prof_event_take();
+    const bool ok = stop && hipEventRecord(stop, stream_) == hipSuccess;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!ok) {
+        prof_event_give_locked(stop);
+        prof_event_give_locked(start_);
         return;
     }
-    std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_pending.push_back({cls_, start_, stop, evals_});
 }
 
@@ -376,6 +404,23 @@ struct mcm_chain {
     ChainInfo ci;
     DeviceChain dc;
     void *block = nullptr;
+};
+
+struct mcm_plan {
+    int32_t count = 0, max_dim = 0;
+    int device = -1;
+    std::vector<int32_t> n;
+    std::vector<int64_t> p_off, tab_off;
+    std::vector<ChainInfo> ci;     // per chain, from n and max_dim
+    std::vector<int32_t> wavefront;  // chains outside the tiled range
+    int64_t p_len = 0;              // dims read: p_all[0 .. p_len)
+    TiledPlan tp;
+    void *tables = nullptr;         // device: TileChain records, then TileSeg from seg_off
+    size_t seg_off = 0;
+    ~mcm_plan()
+    {
+        if (tables) (void)hipFree(tables);
+    }
 };
 
 extern "C" {
@@ -464,6 +509,178 @@ mcm_status mcm_solve_batched(int32_t count, const int32_t *n, const int64_t *p_o
     return st;
 }
 
+mcm_status mcm_plan_create(int32_t count, const int32_t *n, const int64_t *p_off,
+                           const int64_t *tab_off, int32_t max_dim, mcm_plan **out)
+{
+    if (out == nullptr) return MCM_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (count < 0 || max_dim < 1) return MCM_ERR_INVALID_ARG;
+    if (count > 0 && (!n || !p_off || !tab_off)) return MCM_ERR_INVALID_ARG;
+    std::unique_ptr<mcm_plan> pl(new (std::nothrow) mcm_plan);
+    if (!pl) return MCM_ERR_NO_MEMORY;
+    pl->count = count;
+    pl->max_dim = max_dim;
+    pl->n.assign(n, n + count);
+    pl->p_off.assign(p_off, p_off + count);
+    pl->tab_off.assign(tab_off, tab_off + count);
+    pl->ci.resize((size_t)count);
+    for (int32_t b = 0; b < count; ++b) {
+        if (p_off[b] < 0 || tab_off[b] < 0 || n[b] < 1) return MCM_ERR_INVALID_ARG;
+        const mcm_status st = chain_bound(n[b], max_dim, &pl->ci[b]);
+        if (st != MCM_OK) return st;
+        if (p_off[b] + n[b] + 1 > pl->p_len) pl->p_len = p_off[b] + n[b] + 1;
+    }
+    if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
+    if (hipGetDevice(&pl->device) != hipSuccess) return MCM_ERR_DEVICE;
+    std::vector<int> ids;
+    for (int32_t b = 0; b < count; ++b) {
+        if (!tiled_accepts(pl->ci[b])) {
+            pl->wavefront.push_back(b);
+            continue;
+        }
+        ids.push_back(plan_add_chain(pl->tp, pl->ci[b], tab_off[b], tab_off[b], p_off[b],
+                                     p_off[b]));
+    }
+    plan_lockstep(pl->tp, ids);
+    if (!pl->tp.launches.empty()) {
+        const size_t bytes = plan_tables_bytes(pl->tp, &pl->seg_off);
+        std::vector<char> host(bytes);
+        plan_tables_write(pl->tp, host.data());
+        if (hipMalloc(&pl->tables, bytes) != hipSuccess) {
+            pl->tables = nullptr;
+            return MCM_ERR_NO_MEMORY;
+        }
+        if (hipMemcpy(pl->tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return MCM_ERR_DEVICE;
+    }
+    *out = pl.release();
+    return MCM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+mcm_status plan_solve(const mcm_plan *pl, const int32_t *p_all, int64_t *m_all, int32_t *s_all,
+                      hipStream_t stream, int pair_min_blocks)
+{
+    if (pl == nullptr || p_all == nullptr) return MCM_ERR_INVALID_ARG;
+    if (pl->count == 0) return MCM_OK;
+    if (!m_all || !s_all) return MCM_ERR_INVALID_ARG;
+    if (((uintptr_t)m_all & 7) != 0 || ((uintptr_t)s_all & 3) != 0) return MCM_ERR_INVALID_ARG;
+    // Every dimension a chain reads must lie in [1, max_dim]: the plan's key
+    // widths were sized for that bound.
+    for (int32_t b = 0; b < pl->count; ++b) {
+        const int32_t *p = p_all + pl->p_off[b];
+        int32_t lo = INT32_MAX, hi = 0;
+        for (int32_t t = 0; t <= pl->n[b]; ++t) {
+            lo = p[t] < lo ? p[t] : lo;
+            hi = p[t] > hi ? p[t] : hi;
+        }
+        if (lo < 1 || hi > pl->max_dim) return MCM_ERR_INVALID_ARG;
+    }
+    int dev = -1;
+    if (hipGetLastError() != hipSuccess || hipGetDevice(&dev) != hipSuccess)
+        return MCM_ERR_DEVICE;
+    if (dev != pl->device) return MCM_ERR_INVALID_ARG;
+
+    const size_t np = (size_t)pl->p_len;
+    void *dims = nullptr;
+    mcm_status st = upload_blob(stream, &dims, np * sizeof(int32_t),
+                                [&](char *h) { memcpy(h, p_all, np * sizeof(int32_t)); });
+    if (st != MCM_OK) return st;
+    double *pd = nullptr;
+    if (ws_alloc((void **)&pd, np * sizeof(double), stream) != hipSuccess) {
+        ws_free(dims, stream);
+        return MCM_ERR_NO_MEMORY;
+    }
+    const int32_t *p_dev = (const int32_t *)dims;
+    st = widen_dims(p_dev, pd, np, stream);
+    if (st == MCM_OK && pl->tables) {
+        TiledPlan tp_view;  // shares nothing mutable: a copy only when the threshold differs
+        const TiledPlan *tp = &pl->tp;
+        if (pair_min_blocks != pl->tp.pair_min_blocks) {
+            tp_view = pl->tp;
+            tp_view.pair_min_blocks = pair_min_blocks;
+            tp = &tp_view;
+        }
+        st = exec_tiled_plan(*tp, (const TileChain *)pl->tables,
+                             (const TileSeg *)((const char *)pl->tables + pl->seg_off), p_dev, pd,
+                             m_all, s_all, nullptr, stream);
+    }
+    for (size_t u = 0; u < pl->wavefront.size() && st == MCM_OK; ++u) {
+        const int32_t b = pl->wavefront[u];
+        DeviceChain dc;
+        dc.p = p_dev + pl->p_off[b];
+        dc.pd = pd + pl->p_off[b];
+        st = run_wavefront(dc, pl->ci[b], m_all + pl->tab_off[b], s_all + pl->tab_off[b], stream);
+    }
+    ws_free(pd, stream);
+    ws_free(dims, stream);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+mcm_status mcm_plan_solve(const mcm_plan *plan, const int32_t *p_all, int64_t *m_all,
+                          int32_t *s_all, hipStream_t stream)
+{
+    if (plan == nullptr) return MCM_ERR_INVALID_ARG;
+    return plan_solve(plan, p_all, m_all, s_all, stream, plan->tp.pair_min_blocks);
+}
+
+mcm_status mcm_plan_autotune(mcm_plan *plan, const int32_t *p_all, int64_t *m_all,
+                             int32_t *s_all, hipStream_t stream, int32_t *choice)
+{
+    if (plan == nullptr) return MCM_ERR_INVALID_ARG;
+    if (plan->count == 0 || plan->tables == nullptr) {
+        if (choice) *choice = plan->tp.pair_min_blocks;
+        return MCM_OK;
+    }
+    // Candidate closure thresholds: paired closures for launches with more
+    // than this many tiles.  Each candidate is run twice; the second run is
+    // timed with events on the caller's stream.
+    const int cus = device_cus();
+    const int cand[] = {cus, cus / 2, 2 * cus, 4 * cus};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return MCM_ERR_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return MCM_ERR_DEVICE;
+    }
+    mcm_status st = MCM_OK;
+    float best_ms = 0.f;
+    int best = cus;
+    for (int c = 0; c < (int)(sizeof(cand) / sizeof(cand[0])) && st == MCM_OK; ++c) {
+        st = plan_solve(plan, p_all, m_all, s_all, stream, cand[c]);
+        if (st != MCM_OK) break;
+        if (hipEventRecord(e0, stream) != hipSuccess) st = MCM_ERR_DEVICE;
+        if (st == MCM_OK) st = plan_solve(plan, p_all, m_all, s_all, stream, cand[c]);
+        if (st == MCM_OK && hipEventRecord(e1, stream) != hipSuccess) st = MCM_ERR_DEVICE;
+        float ms = 0.f;
+        if (st == MCM_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = MCM_ERR_DEVICE;
+        if (st == MCM_OK && (c == 0 || ms < best_ms)) {
+            best_ms = ms;
+            best = cand[c];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != MCM_OK) return st;
+    plan->tp.pair_min_blocks = best;
+    if (choice) *choice = best;
+    return MCM_OK;
+}
+
+void mcm_plan_destroy(mcm_plan *plan)
+{
+    delete plan;
+}
+
 mcm_status mcm_chain_create(const int32_t *p, int32_t n, hipStream_t stream, mcm_chain **out)
 {
     if (out == nullptr) return MCM_ERR_INVALID_ARG;
@@ -509,12 +726,14 @@ mcm_status mcm_solve(const int32_t *p, int32_t n, int64_t *m_out, int32_t *s_out
     return mcm_solve_algo(p, n, m_out, s_out, MCM_ALGO_AUTO, stream);
 }
 
-void mcm_profile_enable(int32_t on)
+void mcm_profile_enable_mask(uint32_t mask)
 {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     prof_clear_locked();
-    g_prof_on.store(on ? 1 : 0);
+    g_prof_mask.store(mask & ((1u << KC_COUNT) - 1u));
 }
+
+void mcm_profile_enable(int32_t on) { mcm_profile_enable_mask(on ? ~0u : 0u); }
 
 mcm_status mcm_profile_read(int32_t kernel_class, double *total_ms, int64_t *launches,
                             double *split_evals)

@@ -42,6 +42,8 @@ struct DeviceChain {
 
 // Host validation of a chain (no device call); fills ci on success.
 mcm_status check_chain(const int32_t *p, int32_t n, ChainInfo *ci);
+// The facts of any chain of n matrices whose dims are at most pmax.
+mcm_status chain_bound(int32_t n, int32_t pmax, ChainInfo *ci);
 
 // Enqueue a copy of `bytes` host bytes, written by `fill` into pinned
 // staging memory, to the existing device buffer `dst` on `stream`.
@@ -241,6 +243,8 @@ struct TiledPlan {
     bool lone = false;                 // one chain: fit bulk chunks to the GPU's slots
     int cus = 0;                       // lone: compute units of the device
     int slots_per_cu = 0;              // lone: resident k_bulk workgroups per CU
+    int pair_min_blocks = 0;           // closures with more workgroups use the paired
+                                       // shape; 0: the device's CU count
     bool uses_aux = false;             // some launch runs on the aux stream
     int last_main = -1;                // latest launch on the caller's stream
     int last_close = -1;               // latest closure launch
@@ -289,5 +293,14 @@ mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double 
                           int64_t *m_all, int32_t *s_all, uint64_t *part_ext,
                           hipStream_t stream,
                           const ObstWeights *ob = nullptr);
+// The device tables of a plan: TileChain records, then (from *seg_offset,
+// 256-byte aligned) TileSeg records.  plan_tables_write fills that layout.
+size_t plan_tables_bytes(const TiledPlan &plan, size_t *seg_offset);
+void plan_tables_write(const TiledPlan &plan, char *dst);
+// run_tiled_plan with the plan's tables already on the device.
+mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const TileSeg *segs,
+                           const int32_t *p, const double *pd, int64_t *m_all, int32_t *s_all,
+                           uint64_t *part_ext, hipStream_t stream,
+                           const ObstWeights *ob = nullptr);
 
 }  // namespace mcm

@@ -144,6 +144,36 @@ def test_batched_rejects_bad_input_before_device(lib):
     assert np.all(m == 7) and np.all(s == 7)
 
 
+def test_plan_rejects_bad_input_before_device(lib):
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    i64 = ctypes.POINTER(ctypes.c_int64)
+
+    def create(ns, p_off, tab, max_dim, count=None):
+        ns = np.asarray(ns, dtype=np.int32)
+        p_off = np.asarray(p_off, dtype=np.int64)
+        tab = np.asarray(tab, dtype=np.int64)
+        h = ctypes.c_void_p()
+        st = lib.mcm_plan_create(ns.size if count is None else count, ns.ctypes.data_as(i32),
+                                 p_off.ctypes.data_as(i64), tab.ctypes.data_as(i64), max_dim,
+                                 ctypes.byref(h))
+        assert not h.value
+        return st
+
+    assert create([2, 0], [0, 0], [0, 4], 8) == binding.ERR_INVALID_ARG       # n = 0
+    assert create([2], [-1], [0], 8) == binding.ERR_INVALID_ARG               # offset
+    assert create([2], [0], [-4], 8) == binding.ERR_INVALID_ARG               # table offset
+    assert create([2], [0], [0], 0) == binding.ERR_INVALID_ARG                # max_dim
+    assert create([2], [0], [0], 1 << 21) == binding.ERR_OVERFLOW             # 1 * (2^21)^3
+    assert create([2], [0], [0], 8, count=-1) == binding.ERR_INVALID_ARG
+    p = np.array([3, 4, 5], dtype=np.int32)
+    m = np.zeros(4, dtype=np.int64)
+    s = np.zeros(4, dtype=np.int32)
+    assert lib.mcm_plan_solve(None, p.ctypes.data_as(i32), ctypes.c_void_p(m.ctypes.data),
+                              ctypes.c_void_p(s.ctypes.data), ctypes.c_void_p(0)) == \
+        binding.ERR_INVALID_ARG
+    lib.mcm_plan_destroy(None)   # NULL is ignored
+
+
 def test_server_request_bytes(lib):
     assert binding.server_request_bytes([3, 0, 4]) == 0
     small = binding.server_request_bytes([3, 4, 5])

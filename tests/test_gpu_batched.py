@@ -100,3 +100,72 @@ def test_batched_4096_config():
     batch = workloads.batched_4096()
     off, m_all, s_all = run_batch(batch)
     check_against_oracle(batch, off, m_all, s_all)
+
+
+def _plan_solve(plan, p_all, total, autotune=False):
+    import torch
+    m_all = torch.full((max(total, 1),), -9, dtype=torch.int64, device="cuda")
+    s_all = torch.full((max(total, 1),), -9, dtype=torch.int32, device="cuda")
+    choice = plan.autotune(p_all, m_all, s_all) if autotune else None
+    plan.solve_into(p_all, m_all, s_all)
+    torch.cuda.synchronize()
+    return m_all.cpu().numpy(), s_all.cpu().numpy(), choice
+
+
+def test_plan_reused_for_new_dims():
+    # One plan, solved for two dims arrays of the same shape.
+    rng = np.random.default_rng(12)
+    ns = [int(rng.integers(1, 330)) for _ in range(30)] + [64, 65, 128, 1]
+    first = workloads.make_batch([workloads.uniform_dims(n, 1, 1024, 200 + t)
+                                  for t, n in enumerate(ns)])
+    second = workloads.make_batch([workloads.uniform_dims(n, 1, 1024, 400 + t)
+                                   for t, n in enumerate(ns)])
+    assert np.array_equal(first.p_off, second.p_off)
+    off = binding.table_offsets(first.ns)
+    total = int(off[-1] + int(first.ns[-1]) ** 2)
+    _say(f"[gpu] plan count={len(ns)} max_dim=1024")
+    with binding.Plan(first.ns, first.p_off, off, 1024) as plan:
+        for batch in (first, second):
+            m_all, s_all, _ = _plan_solve(plan, batch.p_all, total)
+            check_against_oracle(batch, off, m_all, s_all)
+
+
+def test_plan_wavefront_chains():
+    # A dims bound outside the fp64-exact range sends every chain of the
+    # plan to the int64 wavefront.
+    chains = [workloads.uniform_dims(n, (1 << 19) - 9, 1 << 19, 30 + n) for n in (1, 2, 7, 20)]
+    batch = workloads.make_batch(chains)
+    off = binding.table_offsets(batch.ns)
+    total = int(off[-1] + int(batch.ns[-1]) ** 2)
+    _say("[gpu] plan wavefront max_dim=2^19")
+    with binding.Plan(batch.ns, batch.p_off, off, 1 << 19) as plan:
+        m_all, s_all, _ = _plan_solve(plan, batch.p_all, total)
+    check_against_oracle(batch, off, m_all, s_all)
+
+
+def test_plan_rejects_dims_above_bound():
+    import torch
+    batch = workloads.make_batch([workloads.uniform_dims(40, 1, 100, 3)])
+    off = binding.table_offsets(batch.ns)
+    m_all = torch.full((1600,), -9, dtype=torch.int64, device="cuda")
+    s_all = torch.full((1600,), -9, dtype=torch.int32, device="cuda")
+    with binding.Plan(batch.ns, batch.p_off, off, 50) as plan:
+        with pytest.raises(binding.MCMError):
+            plan.solve_into(batch.p_all, m_all, s_all)   # dims up to 100 > 50
+    torch.cuda.synchronize()
+    assert bool((m_all == -9).all()) and bool((s_all == -9).all())
+
+
+def test_plan_autotuned_4096_config():
+    # The batched benchmark workload through an autotuned plan: every chain
+    # equal to mcm_solve_batched's tables, a sample checked against the oracle.
+    batch = workloads.batched_4096()
+    off, m_ref, s_ref = run_batch(batch)
+    total = m_ref.size
+    _say("[gpu] plan autotune count=4096")
+    with binding.Plan(batch.ns, batch.p_off, off, 256) as plan:
+        m_all, s_all, choice = _plan_solve(plan, batch.p_all, total, autotune=True)
+    assert choice >= 1
+    assert np.array_equal(m_all, m_ref) and np.array_equal(s_all, s_ref)
+    sample = np.random.default_rng(0).choice(batch.ns.size, 128, replace=False)
+    check_against_oracle(batch, off, m_all, s_all, which=sample)
