@@ -204,21 +204,30 @@ struct BulkLds {
 // rows of one column; with G = 8 two row groups reading adjacent columns,
 // whose starts differ by CSTR = 72 = 8 (mod 16) doubles.  Row T is a spare
 // so slot addresses never need clamping.
+// The sweep reads column cc of the DJ table through its base offset, which a
+// lane advances as its cc grows by one (dj_next), so no per-step multiply.
 struct CloseLdsFull {
     double DJt[T][CSTR];   // DJt[c][q] = DJ[q][c] * 2^kb + T + q - 1 (1 <= q <= c), else 0
     double Xt[T][CSTR];    // Xt[c][q]: bulk key, then final cost * 2^kb of cell (q, c)
     int32_t Ks[T][T + 1];  // bulk split, then final split
     double pJs[T + 1];     // p[col0 + q]
-    __device__ double dj_at(int c, int j) const { return DJt[c][j + 1]; }  // DJ[j+1][c]
     __device__ double &dj(int q, int c) { return DJt[c][q]; }
+    // Base of column c is c * CSTR (the same as Xt's); DJ[j+1][c] sits at
+    // base + j + 1.
+    static constexpr bool kPacked = false;
+    __device__ static int dj_next(int base, int) { return base + CSTR; }
+    __device__ double dj_at_base(int base, int j) const { return (&DJt[0][0])[base + j + 1]; }
 };
 struct CloseLdsPacked {
     double DJp[kDJPacked];  // column c from dj_packed_base(c): DJ[q][c] at q - 1
     double Xt[T][CSTR];
     int32_t Ks[T][T + 1];
     double pJs[T + 1];
-    __device__ double dj_at(int c, int j) const { return DJp[dj_packed_base(c) + j]; }
     __device__ double &dj(int q, int c) { return DJp[dj_packed_base(c) + q - 1]; }
+    // dj_packed_base(c + 1) = dj_packed_base(c) + c + ((8 - c) & 15).
+    static constexpr bool kPacked = true;
+    __device__ static int dj_next(int base, int c) { return base + c + ((8 - c) & 15); }
+    __device__ double dj_at_base(int base, int j) const { return DJp[base + j]; }
 };
 
 // ------------------------------------------------------------------------
@@ -409,15 +418,16 @@ struct CloseRegs {
 // (r, cc).  Every (b) slot is read: a slot whose cell is not final yet still
 // holds Xrow = 2^62, so whatever DJ value it meets, its term loses.
 template <int G, int T0, class Lds>  // T0: first (a) slot any row of this wave uses
-__device__ __forceinline__ double close_step(const CloseRegs<G> &R, const Lds &L, int cc, int g,
-                                             double pJc)
+__device__ __forceinline__ double close_step(const CloseRegs<G> &R, const Lds &L, int xo, int djb,
+                                             int g, double pJc)
 {
     constexpr int CS = CloseShape<G>::CS;
     double xa[CS], xb[CS];
+    const double *__restrict__ xcol = &L.Xt[0][0] + xo;  // column cc of Xt
 #pragma unroll
-    for (int t = T0; t < CS; ++t) xa[t] = L.Xt[cc][t * G + g + 1];
+    for (int t = T0; t < CS; ++t) xa[t] = xcol[t * G + g + 1];
 #pragma unroll
-    for (int t = 0; t < CS; ++t) xb[t] = L.dj_at(cc, t * G + g);
+    for (int t = 0; t < CS; ++t) xb[t] = L.dj_at_base(djb, t * G + g);
     // Independent terms, then a balanced min tree.
     double v[CS];
 #pragma unroll
@@ -435,12 +445,12 @@ __device__ __forceinline__ double close_step(const CloseRegs<G> &R, const Lds &L
 // close_step with its first (a) slot t0 (wave-uniform) as a template argument.
 template <int G, int T0, class Lds>
 __device__ __forceinline__ double close_step_at(int t0, const CloseRegs<G> &R, const Lds &L,
-                                                int cc, int g, double pJc)
+                                                int xo, int djb, int g, double pJc)
 {
     if constexpr (T0 + 1 < CloseShape<G>::CS) {
-        if (t0 > T0) return close_step_at<G, T0 + 1>(t0, R, L, cc, g, pJc);
+        if (t0 > T0) return close_step_at<G, T0 + 1>(t0, R, L, xo, djb, g, pJc);
     }
-    return close_step<G, T0>(R, L, cc, g, pJc);
+    return close_step<G, T0>(R, L, xo, djb, g, pJc);
 }
 
 // OB: the optimal-BST weights (pd_all then holds zeros, so every product
@@ -572,18 +582,29 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
     }
     __syncthreads();
 
-    // The sweep is the critical path of the solve.
+    // The sweep is the critical path of the solve.  A row's clamped column
+    // cc grows by at most one per step the wave runs (those steps are
+    // consecutive and the first has every cc = 0), so the packed DJ column
+    // base advances by addition instead of its closed form.
     __builtin_amdgcn_s_setprio(3);
     const int wmax = (T - 1) + (nJ - 1);
+    int cc_run = 0, djb = 0;
     for (int w = 0; w <= wmax; ++w) {
         const int c = w - (T - 1 - r);
         const int c_lo = w - (T - 1 - CROWS * h);  // c of the wave's first row
         const int c_hi = c_lo + CROWS - 1;         // ... and of its last row
         if (c_hi >= 0 && c_lo < nJ) {              // wave-uniform
             const int cc = min(max(c, 0), nJ - 1);
+            const int xo = __mul24(cc, CSTR);  // column cc of Xt
+            if constexpr (Lds::kPacked) {
+                djb = cc != cc_run ? Lds::dj_next(djb, cc_run) : djb;
+                cc_run = cc;
+            } else {
+                djb = xo;
+            }
             const double pJc = L.pJs[cc + 1];
-            const double xbulk = L.Xt[cc][r];
-            const double best = close_step_at<G, 0>((h * CROWS) / G, R, L, cc, g, pJc);
+            const double xbulk = (&L.Xt[0][0])[xo + r];
+            const double best = close_step_at<G, 0>((h * CROWS) / G, R, L, xo, djb, g, pJc);
             const double fin = fmin(best, xbulk);
             const double base = floor(fin * inv_scale);
             const double cost = OB ? base + (pJc - w_row) : base;
@@ -593,7 +614,7 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
                 for (int t = 0; t < CS; ++t)
                     if (t * G + g == c) R.Xrow[t] = xv;
                 if (g == 0) {
-                    L.Xt[c][r] = xv;
+                    (&L.Xt[0][0])[xo + r] = xv;
                     const int kl = (int)fma(-base, scale, fin);
                     if (kl != T - 1) L.Ks[r][c] = kl < T - 1 ? row0 + kl : col0 + (kl - T);
                 }
@@ -654,7 +675,9 @@ __global__ __launch_bounds__(CloseShape<CG_LONE>::CTH) void k_close_ob(
                                             part_all, ob_hi, ob_lo);
 }
 
-__global__ __launch_bounds__(CloseShape<CG_PAIR>::CTH) void k_close_pair_ob(
+// Four waves per SIMD: without the bound the weight terms take it past the
+// 128 VGPRs that two workgroups per CU allow.
+__global__ __launch_bounds__(CloseShape<CG_PAIR>::CTH, 4) void k_close_pair_ob(
     const TileChain *__restrict__ chains, const TileSeg *__restrict__ segs, int nseg,
     int64_t *__restrict__ m_all, int32_t *__restrict__ s_all, const double *__restrict__ pd_all,
     const uint64_t *__restrict__ part_all, const double *__restrict__ ob_hi,
