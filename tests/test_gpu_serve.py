@@ -113,3 +113,55 @@ def test_few_large_requests_use_fine_chunks():
     for tag, p in reqs.items():
         om, os_ = oracle.fill(p, threads=oracle.default_threads())
         assert np.array_equal(got[tag][0], om) and np.array_equal(got[tag][1], os_), f"request {tag}"
+
+
+def _d2d(dst, src_ptr: int, nbytes: int):
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    hip.hipMemcpy.restype = ctypes.c_int
+    assert hip.hipMemcpy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src_ptr), nbytes,
+                         3) == 0   # hipMemcpyDeviceToDevice
+
+
+def test_benchmark_stream_served_equals_alone():
+    # The benchmark's 1000-request stream (seed 4, Poisson 600/s, n log-uniform
+    # in [8, 4096]): every served table equals the same chain solved alone,
+    # compared on the device; requests with n <= 192 also against the oracle.
+    import torch
+    st = workloads.serving_stream(count=1000, rate=600.0, seed=4)
+    batch = st.batch
+    count = int(batch.ns.size)
+    _say(f"[gpu] serve benchmark stream, {count} requests, max n={int(batch.ns.max())}")
+    done = 0
+    checked_oracle = 0
+    with binding.Server(24 << 30, 256) as srv:
+        t0 = binding.clock_now()
+        arrive = t0 + st.arrivals
+        nxt = 0
+        while done < count:
+            now = binding.clock_now()
+            while nxt < count and arrive[nxt] <= now:
+                srv.submit(batch.dims(nxt), nxt)
+                nxt += 1
+            for info in srv.poll():
+                i, n = int(info.tag), int(info.n)
+                assert info.status == binding.OK, f"request {i}"
+                m_srv = torch.empty(n * n, dtype=torch.int64, device="cuda")
+                s_srv = torch.empty(n * n, dtype=torch.int32, device="cuda")
+                _d2d(m_srv, info.m, n * n * 8)
+                _d2d(s_srv, info.s, n * n * 4)
+                srv.release(i)
+                p = batch.dims(i)
+                m_alone, s_alone = binding.solve(p)
+                torch.cuda.synchronize()
+                assert torch.equal(m_srv.view(n, n), m_alone), f"request {i} (n={n}): m"
+                assert torch.equal(s_srv.view(n, n), s_alone), f"request {i} (n={n}): s"
+                if n <= 192:
+                    om, os_ = oracle.fill(p)
+                    assert np.array_equal(m_srv.view(n, n).cpu().numpy(), om), f"request {i}"
+                    assert np.array_equal(s_srv.view(n, n).cpu().numpy(), os_), f"request {i}"
+                    checked_oracle += 1
+                done += 1
+    _say(f"[gpu] {done} served tables equal alone; {checked_oracle} also equal the oracle")
+    assert checked_oracle > 300
