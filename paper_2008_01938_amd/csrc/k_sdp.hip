@@ -19,6 +19,10 @@
 //     whose lane l holds element l: at step r' lane r' is final, and every
 //     lane l with l - r' among the offsets folds it in, a register update per
 //     step instead of a memory round trip.
+// Far terms with offsets of two blocks or more read only elements that were
+// final before the previous block's near kernel started, so they are folded
+// on a second stream beside it (see sdp_launch); the rest stay on the
+// caller's stream between two near launches.
 // The paper's pipeline (Fig. 2) instead assigns one thread per offset and
 // advances one element per step; that keeps k threads busy, while this
 // layout spreads the bulk of the work (the far terms) over all CUs and keeps
@@ -225,16 +229,78 @@ mcm_status sdp_launch(const SdpPlan &pl, int32_t *st, hipStream_t stream)
     const size_t far_lds = (size_t)(((pl.chunk_max + 3) & ~3) + kFarTile + pl.span_max) * 4;
     const size_t near_lds = (size_t)(2 * pl.B + pl.kn) * 4;
     const int tiles = (pl.B + kFarTile - 1) / kFarTile;
-    for (int64_t t = pl.a1; t < pl.n; t += pl.B) {
-        const int tend = (int)(t + pl.B < pl.n ? t + pl.B : pl.n);
-        hipLaunchKernelGGL(k_sdp_far<OP>, dim3((unsigned)(tiles * pl.nchunks)), dim3(kFarTile),
-                           far_lds, stream, st, pl.part, pl.a, pl.chunks, pl.nchunks, (int)t,
-                           tend);
-        hipLaunchKernelGGL(k_sdp_near<OP>, dim3(1), dim3(kNearThreads), near_lds, stream, st,
+    const int64_t nblocks = (cnt + pl.B - 1) / pl.B;
+    const int nold = pl.nchunks_old, nnew = pl.nchunks - pl.nchunks_old;
+    auto far = [&](hipStream_t q, const int2 *ch, int nch, int64_t t, int tend) {
+        hipLaunchKernelGGL(k_sdp_far<OP>, dim3((unsigned)(tiles * nch)), dim3(kFarTile), far_lds,
+                           q, st, pl.part, pl.a, ch, nch, (int)t, tend);
+    };
+    auto near = [&](hipStream_t q, int64_t t, int tend) {
+        hipLaunchKernelGGL(k_sdp_near<OP>, dim3(1), dim3(kNearThreads), near_lds, q, st,
                            pl.part, pl.near_a, pl.kn, pl.cnt_le, pl.seq_mask, (int)t, tend, pl.B);
-        if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
+    };
+    if (nold == 0 || nblocks < 3) {
+        for (int64_t t = pl.a1; t < pl.n; t += pl.B) {
+            const int tend = (int)(t + pl.B < pl.n ? t + pl.B : pl.n);
+            far(stream, pl.chunks, pl.nchunks, t, tend);
+            near(stream, t, tend);
+            if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
+        }
+        return MCM_OK;
     }
-    return MCM_OK;
+    // Two streams.  The old terms of block b (offsets >= 2B) read elements
+    // before block b-1, final once near(b-2) is done, so they are folded on
+    // the library's aux stream while near(b-1) runs; the caller's stream
+    // runs the new terms of b, waits for the old ones, then near(b).
+    //   - far_old(b) waits for the launch before near(b-1) (which follows
+    //     near(b-2)), then a short pause, so near(b-1) reaches a CU first;
+    //   - near asks for LDS enough that no far workgroup fits beside it
+    //     (a latency-bound workgroup sharing its CU runs markedly slower).
+    StreamSet ss;
+    if (acquire_streams((int)(2 * nblocks + 2), &ss) != MCM_OK) return MCM_ERR_DEVICE;
+    hipEvent_t *ev_old = ss.events.data() + 2, *ev_pre = ev_old + nblocks;
+    const size_t lds_cu = 163840;
+    const size_t near_excl = far_lds < lds_cu ? lds_cu - far_lds + 1024 : near_lds;
+    const size_t near_lds2 = near_excl > near_lds && near_excl <= lds_cu ? near_excl : near_lds;
+    mcm_status rc = MCM_OK;
+    if (hipEventRecord(ss.events[0], stream) != hipSuccess ||
+        hipStreamWaitEvent(ss.aux, ss.events[0], 0) != hipSuccess)
+        rc = MCM_ERR_DEVICE;
+    const bool forked = rc == MCM_OK;
+    for (int64_t b = 0; b < nblocks && rc == MCM_OK; ++b) {
+        const int64_t t = pl.a1 + b * pl.B;
+        const int tend = (int)(t + pl.B < pl.n ? t + pl.B : pl.n);
+        if (b >= 1) {
+            if (hipStreamWaitEvent(ss.aux, ev_pre[b - 1], 0) != hipSuccess ||
+                launch_delay(ss.aux) != MCM_OK) {
+                rc = MCM_ERR_DEVICE;
+                break;
+            }
+        }
+        far(ss.aux, pl.chunks, nold, t, tend);
+        if (hipGetLastError() != hipSuccess || hipEventRecord(ev_old[b], ss.aux) != hipSuccess) {
+            rc = MCM_ERR_DEVICE;
+            break;
+        }
+        if (nnew > 0) far(stream, pl.chunks + nold, nnew, t, tend);
+        if (hipGetLastError() != hipSuccess ||
+            hipStreamWaitEvent(stream, ev_old[b], 0) != hipSuccess ||
+            hipEventRecord(ev_pre[b], stream) != hipSuccess) {
+            rc = MCM_ERR_DEVICE;
+            break;
+        }
+        hipLaunchKernelGGL(k_sdp_near<OP>, dim3(1), dim3(kNearThreads), near_lds2, stream, st,
+                           pl.part, pl.near_a, pl.kn, pl.cnt_le, pl.seq_mask, (int)t, tend, pl.B);
+        if (hipGetLastError() != hipSuccess) rc = MCM_ERR_DEVICE;
+    }
+    if (forked) {
+        // Join: the caller's stream continues after everything on aux.
+        if (hipEventRecord(ss.events[1], ss.aux) != hipSuccess ||
+            hipStreamWaitEvent(stream, ss.events[1], 0) != hipSuccess)
+            rc = MCM_ERR_DEVICE;
+    }
+    release_streams(ss);
+    return rc;
 }
 
 }  // namespace

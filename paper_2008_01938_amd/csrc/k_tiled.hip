@@ -715,6 +715,16 @@ long long delay_ticks_for_device()
     return (long long)khz * 4 / 1000;
 }
 
+}  // namespace
+
+mcm_status launch_delay(hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_delay, dim3(1), dim3(64), 0, stream, delay_ticks_for_device());
+    return hipGetLastError() == hipSuccess ? MCM_OK : MCM_ERR_DEVICE;
+}
+
+namespace {
+
 // ------------------------------------------------------------------------
 // Host planning.
 // ------------------------------------------------------------------------

@@ -114,6 +114,10 @@ struct StreamSet {
 mcm_status acquire_streams(int count, StreamSet *out);
 // Returns the events once every wait on them has been enqueued.
 void release_streams(StreamSet &ss);
+// Enqueue a pause of about 4 microseconds (one 64-thread workgroup waiting
+// on the wall clock) on `stream`: work behind it on that stream reaches the
+// CUs after work another stream has just dispatched.
+mcm_status launch_delay(hipStream_t stream);
 // Compute units of the current device, and resident k_bulk workgroups per CU.
 int device_cus();
 int bulk_blocks_per_cu();
@@ -173,6 +177,7 @@ struct SdpPlan {
     const int32_t *a = nullptr;   // device, k offsets descending
     const int2 *chunks = nullptr; // device, (j0, j1) offset chunks of the far kernel
     int32_t nchunks = 0, chunk_max = 0, span_max = 0;
+    int32_t nchunks_old = 0;      // the first chunks, every offset >= 2B (see run_sdp)
     const int32_t *near_a = nullptr;     // device, offsets < B ascending
     int32_t kn = 0;
     const int32_t *cnt_le = nullptr;     // device, B prefix counts of near_a

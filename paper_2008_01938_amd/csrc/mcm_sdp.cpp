@@ -11,7 +11,8 @@ using namespace mcm;
 namespace {
 
 constexpr int kSdpBlock = 2048;      // elements per far/near launch pair
-constexpr int kChunkMax = 1024;      // offsets per far workgroup
+constexpr int kChunkMax = 1024;      // offsets per far workgroup (old terms)
+constexpr int kChunkMaxNew = 64;     // ... for the terms on the critical path
 constexpr int kSpanMax = 8192 - 256; // a[j0] - a[j1-1] within a chunk
 
 size_t align8(size_t x) { return (x + 7) / 8 * 8; }
@@ -34,14 +35,24 @@ mcm_status mcm_sdp_solve(const int32_t *a, int32_t k, int32_t op, int32_t *st, i
 
     const int B = kSdpBlock;
     // Far kernel chunks: runs of consecutive offsets, at most kChunkMax of
-    // them spanning at most kSpanMax values (their sources fit in LDS).
+    // them spanning at most kSpanMax values (their sources fit in LDS).  No
+    // chunk mixes offsets >= 2B with smaller ones: the former ("old" terms)
+    // read only elements two blocks back and are folded ahead of time.
     std::vector<int32_t> chunks;
-    int chunk_max = 0, span_max = 0;
+    int chunk_max = 0, span_max = 0, nchunks_old = 0;
+    const int32_t old_min = 2 * kSdpBlock;
     for (int32_t j0 = 0; j0 < k;) {
+        const bool old = a[j0] >= old_min;
+        // A far workgroup's time grows with its offsets, so the new terms,
+        // folded between two near launches, come in short chunks.
+        const int32_t cmax = old ? kChunkMax : kChunkMaxNew;
         int32_t j1 = j0 + 1;
-        while (j1 < k && j1 - j0 < kChunkMax && a[j0] - a[j1] <= kSpanMax) ++j1;
+        while (j1 < k && j1 - j0 < cmax && a[j0] - a[j1] <= kSpanMax &&
+               (a[j1] >= old_min) == old)
+            ++j1;
         chunks.push_back(j0);
         chunks.push_back(j1);
+        if (old) ++nchunks_old;
         if (j1 - j0 > chunk_max) chunk_max = j1 - j0;
         if (a[j0] - a[j1 - 1] > span_max) span_max = a[j0] - a[j1 - 1];
         j0 = j1;
@@ -90,6 +101,7 @@ mcm_status mcm_sdp_solve(const int32_t *a, int32_t k, int32_t op, int32_t *st, i
     pl.a = (const int32_t *)((char *)blob + o_a);
     pl.chunks = (const int2 *)((char *)blob + o_chunks);
     pl.nchunks = nchunks;
+    pl.nchunks_old = nchunks_old;
     pl.chunk_max = chunk_max;
     pl.span_max = span_max;
     pl.near_a = (const int32_t *)((char *)blob + o_near);
