@@ -102,3 +102,22 @@ def test_table1_configs_sampled(name):
     for op in ("min", "add"):
         st = _run(a, init, n, op)
         _sampled_recurrence(st, a, init, op, 1500, 3)
+
+
+@pytest.mark.parametrize("op", sdp.OPS)
+def test_old_and_new_offsets_full(op):
+    # Offsets on both sides of two blocks (4096), several blocks and a ragged
+    # last one: the far terms split between the two streams.
+    rng = np.random.default_rng(21)
+    a = np.sort(rng.choice(12000, size=3000, replace=False) + 1)[::-1].astype(np.int32)
+    n = int(a[0]) + 5 * 2048 + 777
+    init = rng.integers(-(1 << 30), 1 << 30, size=int(a[0])).astype(np.int32)
+    assert (a >= 4096).any() and (a < 4096).any()
+    assert np.array_equal(_run(a, init, n, op), sdp.solve(a, init, n, op))
+
+
+def test_consecutive_beyond_two_blocks():
+    # Fig. 4's worst case with k above 2B: offsets k..1 fall on both sides.
+    a, init = workloads.sdp_instance(0, 6000, 2, "consecutive")
+    n = 6000 + 4 * 2048 + 5
+    assert np.array_equal(_run(a, init, n, "min"), sdp.solve(a, init, n, "min"))
