@@ -169,3 +169,24 @@ def test_plan_autotuned_4096_config():
     assert np.array_equal(m_all, m_ref) and np.array_equal(s_all, s_ref)
     sample = np.random.default_rng(0).choice(batch.ns.size, 128, replace=False)
     check_against_oracle(batch, off, m_all, s_all, which=sample)
+
+
+def test_plan_empty_and_mixed_paths():
+    import torch
+    # An empty plan solves nothing.
+    m = torch.zeros(4, dtype=torch.int64, device="cuda")
+    s = torch.zeros(4, dtype=torch.int32, device="cuda")
+    with binding.Plan([], [], [], 8) as plan:
+        plan.solve_into(np.array([1], dtype=np.int32), m, s)
+    torch.cuda.synchronize()
+    assert int(m.abs().sum()) == 0 and int(s.abs().sum()) == 0
+    # A dims bound of 2^15 keeps n = 1, 2 in the fp64-exact tiled range and
+    # sends longer chains to the int64 wavefront: both paths in one plan.
+    chains = [workloads.uniform_dims(n, 1, 1 << 15, 60 + n) for n in (2, 5, 1, 40, 2, 130)]
+    batch = workloads.make_batch(chains)
+    off = binding.table_offsets(batch.ns)
+    total = int(off[-1] + int(batch.ns[-1]) ** 2)
+    _say("[gpu] plan mixed paths max_dim=2^15")
+    with binding.Plan(batch.ns, batch.p_off, off, 1 << 15) as plan:
+        m_all, s_all, _ = _plan_solve(plan, batch.p_all, total)
+    check_against_oracle(batch, off, m_all, s_all)
