@@ -1169,6 +1169,10 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
     StreamSet ss;
     if (aux && acquire_streams(nrec + 2, &ss) != MCM_OK) st = MCM_ERR_DEVICE;
     std::vector<hipEvent_t> rec(plan.launches.size(), nullptr);
+    // Aux launches the caller's stream waits for hand over a signal token
+    // instead of an event when the device has a signal word (a stream wait
+    // on a value is a shorter hop than an event wait).
+    std::vector<uint64_t> tok(plan.launches.size(), 0);
     int next_ev = 2;
     bool forked = false;
     if (aux && st == MCM_OK) {
@@ -1186,7 +1190,8 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
         hipStream_t q = L.stream == 1 ? ss.aux : stream;
         hipError_t e = hipSuccess;
         if (L.wait >= 0 && plan.launches[L.wait].stream != L.stream)
-            e = hipStreamWaitEvent(q, rec[L.wait], 0);
+            e = tok[L.wait] ? aux_signal_wait(q, tok[L.wait])
+                            : hipStreamWaitEvent(q, rec[L.wait], 0);
         if (e != hipSuccess) {
             st = MCM_ERR_DEVICE;
             break;
@@ -1233,8 +1238,11 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
             e = hipGetLastError();
         }
         if (e == hipSuccess && L.record && aux) {
-            rec[li] = ss.events[next_ev++];
-            e = hipEventRecord(rec[li], q);
+            if (L.stream == 1) tok[li] = aux_signal_write(ss.aux);
+            if (!tok[li]) {
+                rec[li] = ss.events[next_ev++];
+                e = hipEventRecord(rec[li], q);
+            }
         }
         if (e != hipSuccess) st = MCM_ERR_DEVICE;
     }

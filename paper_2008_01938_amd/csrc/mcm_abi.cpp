@@ -254,7 +254,59 @@ std::mutex g_streams_mu;
 std::unordered_map<int, hipStream_t> g_aux;
 std::unordered_map<int, std::vector<hipEvent_t>> g_event_pool;
 std::unordered_map<int, int> g_cus;
+
+// Per-device signal word written only by the aux stream, with increasing
+// tokens (the write is enqueued under g_streams_mu, so the aux stream
+// executes the writes in token order): a wait for "word >= token" on another
+// stream ends once the aux work before that token has finished.
+struct AuxSignal {
+    uint64_t *word = nullptr;
+    uint64_t next = 0;
+    bool tried = false, ok = false;
+};
+std::unordered_map<int, AuxSignal> g_aux_sig;
 }  // namespace
+
+uint64_t aux_signal_write(hipStream_t aux)
+{
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(g_streams_mu);
+    AuxSignal &sig = g_aux_sig[device];
+    if (!sig.tried) {
+        sig.tried = true;
+        int can = 0;
+        if (hipDeviceGetAttribute(&can, hipDeviceAttributeCanUseStreamWaitValue, device) ==
+                hipSuccess &&
+            can &&
+            hipExtMallocWithFlags((void **)&sig.word, sizeof(uint64_t), hipMallocSignalMemory) ==
+                hipSuccess) {
+            // Start from zero before any token is handed out (the allocation
+            // is not cleared); kept until the process ends.
+            sig.ok = hipStreamWriteValue64(aux, sig.word, 0, 0) == hipSuccess &&
+                     hipStreamSynchronize(aux) == hipSuccess;
+        }
+    }
+    if (!sig.ok) return 0;
+    const uint64_t token = sig.next + 1;
+    if (hipStreamWriteValue64(aux, sig.word, token, 0) != hipSuccess) return 0;
+    sig.next = token;
+    return token;
+}
+
+hipError_t aux_signal_wait(hipStream_t stream, uint64_t token)
+{
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return e;
+    uint64_t *word = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_streams_mu);
+        word = g_aux_sig[device].word;
+    }
+    if (!word) return hipErrorInvalidValue;
+    return hipStreamWaitValue64(stream, word, token, hipStreamWaitValueGte, ~(uint64_t)0);
+}
 
 int device_cus()
 {

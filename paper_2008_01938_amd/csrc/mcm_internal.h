@@ -112,6 +112,12 @@ struct StreamSet {
     std::vector<hipEvent_t> events;
 };
 mcm_status acquire_streams(int count, StreamSet *out);
+// Enqueue on the aux stream a write of the next token of the device's aux
+// signal word and return the token (0: no signal word on this device; use an
+// event instead).  aux_signal_wait enqueues on `stream` a wait until the word
+// holds at least `token`.
+uint64_t aux_signal_write(hipStream_t aux);
+hipError_t aux_signal_wait(hipStream_t stream, uint64_t token);
 // Returns the events once every wait on them has been enqueued.
 void release_streams(StreamSet &ss);
 // Enqueue a pause of about 4 microseconds (one 64-thread workgroup waiting
