@@ -278,13 +278,21 @@ mcm_status sdp_launch(const SdpPlan &pl, int32_t *st, hipStream_t stream)
             }
         }
         far(ss.aux, pl.chunks, nold, t, tend);
-        if (hipGetLastError() != hipSuccess || hipEventRecord(ev_old[b], ss.aux) != hipSuccess) {
+        // The old terms are handed to the caller's stream as an aux signal
+        // token when the device has one (a shorter hop), else an event.
+        if (hipGetLastError() != hipSuccess) {
+            rc = MCM_ERR_DEVICE;
+            break;
+        }
+        const uint64_t token = aux_signal_write(ss.aux);
+        if (!token && hipEventRecord(ev_old[b], ss.aux) != hipSuccess) {
             rc = MCM_ERR_DEVICE;
             break;
         }
         if (nnew > 0) far(stream, pl.chunks + nold, nnew, t, tend);
         if (hipGetLastError() != hipSuccess ||
-            hipStreamWaitEvent(stream, ev_old[b], 0) != hipSuccess ||
+            (token ? aux_signal_wait(stream, token)
+                   : hipStreamWaitEvent(stream, ev_old[b], 0)) != hipSuccess ||
             hipEventRecord(ev_pre[b], stream) != hipSuccess) {
             rc = MCM_ERR_DEVICE;
             break;
