@@ -704,7 +704,7 @@ __global__ __launch_bounds__(64) void k_delay(long long ticks)
     while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(8);
 }
 
-// Ticks of the pause before an interior bulk launch: about 4 microseconds.
+// Ticks of a pause (launch_delay): about 4 microseconds.
 long long delay_ticks_for_device()
 {
     int device = 0, khz = 0;
@@ -1027,15 +1027,10 @@ void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
             add_bulk(inter, cs, E, T + bl.int_len, (E - 3) * T + 1 - bl.int_len, bl.int2_ks,
                      bl.int2_nch, bl.int_nch, bl.PT);
     }
-    if (inter.nseg) {
-        // A short pause on the aux stream lets the closure's workgroups
-        // reach their CUs first: a closure workgroup needs a CU of its own,
-        // and interior workgroups dispatched earlier would hold them all.
-        TiledLaunch delay{TK_DELAY, 0, 0, 1, 0.0};
-        delay.stream = 1;
-        push(delay, before_close);
-        plan.last_interior = push(inter, -1);
-    }
+    // The interior starts after the launch before the closure (an event
+    // wait on the aux stream, whose own latency already lets the closure's
+    // workgroups reach their CUs first; a further pause measured slower).
+    if (inter.nseg) plan.last_interior = push(inter, before_close);
 
     // End blocks of D+1 (main stream, after the closure of D).
     TiledLaunch ends{TK_BULK, (int)plan.segs.size(), 0, 0, 0.0};
@@ -1183,7 +1178,6 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
             st = MCM_ERR_DEVICE;
         forked = st == MCM_OK;
     }
-    const long long delay_ticks = aux ? delay_ticks_for_device() : 0;
     const int cus = device_cus();
     for (size_t li = 0; li < plan.launches.size() && st == MCM_OK; ++li) {
         const TiledLaunch &L = plan.launches[li];
@@ -1232,9 +1226,6 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
             else
                 hipLaunchKernelGGL(k_close_pair, dim3(L.blocks), dim3(CloseShape<CG_PAIR>::CTH),
                                    0, q, chains, sg, L.nseg, m_all, s_all, pd, part);
-            e = hipGetLastError();
-        } else {
-            hipLaunchKernelGGL(k_delay, dim3(1), dim3(64), 0, q, delay_ticks);
             e = hipGetLastError();
         }
         if (e == hipSuccess && L.record && aux) {

@@ -92,7 +92,7 @@ struct TileSeg {        // consecutive workgroups of one launch working on one c
 };
 
 enum SegRole { SEG_CLOSE = 0, SEG_BULK = 1 };
-enum TiledKernel { TK_TRI = 0, TK_BULK = 1, TK_CLOSE = 2, TK_DELAY = 3 };
+enum TiledKernel { TK_TRI = 0, TK_BULK = 1, TK_CLOSE = 2 };
 
 struct TiledLaunch {    // one kernel launch of a tiled plan
     int kind;           // TiledKernel
