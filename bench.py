@@ -10,8 +10,8 @@ preallocated.  Prints one JSON line:
   roofline   the bulk kernel (the dominant one) against the fp64 VALU issue
              rate: each split evaluation is an fp64 fma, add and min, i.e.
              3 VALU lane-ops; peak = 256 CUs x 64 lanes x 2.4 GHz.  Its
-             duration is measured with HIP events on the launch stream
-             during the timed steps.  `traffic` comes from the committed
+             duration is measured with HIP events on the launch streams
+             around every launch of the last timed step.  `traffic` comes from the committed
              rocprofv3 FETCH_SIZE/WRITE_SIZE summary, and is null when the
              kernel source changed since it was taken.
   cpu_baseline  the CPU oracle on a bounded window of the same chain.
@@ -417,14 +417,17 @@ def main() -> int:
         chain.solve_into(m, s, algo=algo)
     torch.cuda.synchronize()
 
-    # The timed steps mark only the dominant kernel's launches with events
-    # (every marked launch adds two event records to its stream).
+    # The last timed step marks the dominant kernel's launches with events
+    # (every marked launch adds two event records to its stream, so marking
+    # every step would tax the throughput being measured).
     dom = "bulk" if chosen == "tiled" else "wavefront"
     dom_class = binding.PROF_BULK if dom == "bulk" else binding.PROF_WAVE
-    binding.profile_enable(True, classes=[dom_class])
+    binding.profile_enable(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for step in range(args.steps):
+        if step == args.steps - 1:
+            binding.profile_enable(True, classes=[dom_class])
         chain.solve_into(m, s, algo=algo)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -457,7 +460,7 @@ def main() -> int:
         "kernel": "k_bulk" if dom == "bulk" else "k_wave_diag",
         "ops_per_split_eval": OPS_PER_EVAL,
         "avg_launch_ms": round(avg_s * 1e3, 5),
-        "launches_per_step": d["launches"] / args.steps,
+        "launches_per_step": d["launches"],
     }
     sclk = read_sclk() if dom == "bulk" else None
     if sclk:
