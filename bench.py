@@ -381,6 +381,9 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=600.0, help="Poisson arrivals per second")
     args = ap.parse_args()
 
+    if args.steps < 1 or args.warmup < 0:
+        print("bench.py needs --steps >= 1 and --warmup >= 0", file=sys.stderr)
+        return 2
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver is a "
               "single-device library and multi-GPU runs are not part of this build.",
