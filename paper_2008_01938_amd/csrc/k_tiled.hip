@@ -18,7 +18,9 @@
 // [(I+1)T-1, (I+2)T-2] and [(J-1)T, JT-1], read tiles of tile-diagonal
 // D-1; the interior between them reads only tiles of diagonals <= D-2.
 //
-// k_tri fills the diagonal tiles (all their splits stay inside the tile).
+// k_tri_key fills the diagonal tiles (all their splits stay inside the
+// tile) on fp64 keys; k_tri<true> does it in int64 with the optimal-BST
+// weights.
 // k_bulk: a min-plus-like reduction over a chunk of a tile's bulk range.
 //         The A panel (rows of I, columns k) and the B panel (rows k+1,
 //         columns of J) are staged through LDS; each thread keeps a 4 x 4
@@ -53,7 +55,7 @@ namespace {
 
 constexpr int T = 64;          // tile edge
 constexpr int KC = 16;         // k values staged per LDS round (bulk)
-constexpr int NTH = 256;       // k_tri and k_bulk threads
+constexpr int NTH = 256;       // k_tri, k_tri_key and k_bulk threads
 constexpr double kPad = 4611686018427387904.0;  // 2^62: never wins a min
 
 // The segment of a launch that workgroup b belongs to (segments are sorted
@@ -149,6 +151,67 @@ __global__ __launch_bounds__(NTH) void k_tri(const TileChain *__restrict__ chain
         if (rr < nI && cc < nI) {
             const size_t o = (size_t)(base + rr) * n + base + cc;
             m[o] = rr <= cc ? tv[rr][cc] : tv[cc][rr];
+            s[o] = rr < cc ? base + (int32_t)sv[rr][cc] : -1;
+        }
+    }
+}
+
+// The same diagonal tiles with the exact fp64 keys of the bulk and closure
+// kernels (no weights): a split kl of cell (r, c) is the integer
+//   (m[r][kl] + m[kl+1][c] + p[r] p[kl+1] p[c+1]) * 2^kb + kl  <  2^53,
+// since every candidate cost is below 2^cost_bits and kb <= 53 - cost_bits
+// (and kl < 64 <= 2^kb), so every fma, add and min on it is exact and one
+// fmin picks the smallest cost, then the smallest kl.
+__global__ __launch_bounds__(NTH) void k_tri_key(const TileChain *__restrict__ chains,
+                                                 const TileSeg *__restrict__ segs, int nseg,
+                                                 const double *__restrict__ pd_all,
+                                                 int64_t *__restrict__ m_all,
+                                                 int32_t *__restrict__ s_all)
+{
+    __shared__ double tv[T][T + 1];   // cost * 2^kb of cell (r, c), r <= c
+    __shared__ uint8_t sv[T][T + 4];  // local split (0..T-2) of cell (r, c), r < c
+    __shared__ double ps[T + 1];
+    const int tid = threadIdx.x;
+    const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
+    const TileChain ch = chains[sg.chain];
+    const int32_t n = ch.n;
+    const double *__restrict__ pd = pd_all + ch.pd_off;
+    int64_t *__restrict__ m = m_all + ch.m_off;
+    int32_t *__restrict__ s = s_all + ch.s_off;
+    const double scale = ldexp(1.0, ch.kb), inv_scale = ldexp(1.0, -ch.kb);
+    const int base = (blockIdx.x - sg.first) * T;
+    const int nI = min(T, n - base);
+    for (int q = tid; q <= nI; q += NTH) ps[q] = pd[base + q];
+    for (int r = tid; r < T; r += NTH) tv[r][r] = 0.0;
+    __syncthreads();
+
+    for (int dd = 1; dd < nI; ++dd) {
+        const int cells = nI - dd;
+        int lg = 2;  // log2 L, lanes per cell as in k_tri
+        while (lg < 6 && (cells << (lg + 1)) <= NTH) ++lg;
+        const int L = 1 << lg;
+        const int r = tid >> lg, g = tid & (L - 1);
+        const int c = r + dd;
+        double best = kPad;
+        if (r < cells) {
+            const double prc = ps[r] * ps[c + 1] * scale;
+            for (int kl = r + g; kl < c; kl += L)
+                best = fmin(best, fma(prc, ps[kl + 1], (double)kl) + tv[r][kl] + tv[kl + 1][c]);
+        }
+        for (int off = 1; off < L; off <<= 1) best = fmin(best, __shfl_xor(best, off, 64));
+        if (r < cells && g == 0) {
+            const double cost = floor(best * inv_scale);
+            tv[r][c] = cost * scale;
+            sv[r][c] = (uint8_t)(int)fma(-cost, scale, best);
+        }
+        __syncthreads();
+    }
+
+    for (int idx = tid; idx < T * T; idx += NTH) {
+        const int rr = idx / T, cc = idx % T;
+        if (rr < nI && cc < nI) {
+            const size_t o = (size_t)(base + rr) * n + base + cc;
+            m[o] = (int64_t)((rr <= cc ? tv[rr][cc] : tv[cc][rr]) * inv_scale);
             s[o] = rr < cc ? base + (int32_t)sv[rr][cc] : -1;
         }
     }
@@ -1197,8 +1260,8 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
                 hipLaunchKernelGGL(k_tri<true>, dim3(L.blocks), dim3(NTH), 0, q, chains, sg,
                                    L.nseg, p, m_all, s_all, ob->hi, ob->lo, ob->q);
             else
-                hipLaunchKernelGGL(k_tri<false>, dim3(L.blocks), dim3(NTH), 0, q, chains, sg,
-                                   L.nseg, p, m_all, s_all, nullptr, nullptr, nullptr);
+                hipLaunchKernelGGL(k_tri_key, dim3(L.blocks), dim3(NTH), 0, q, chains, sg, L.nseg,
+                                   pd, m_all, s_all);
             e = hipGetLastError();
         } else if (L.kind == TK_BULK) {
             ProfileScope ps(KC_BULK, q, L.evals);
