@@ -7,14 +7,27 @@ the chain already resident in device memory and the output tables
 preallocated.  Prints one JSON line:
 
   value      split evaluations per second, (n^3 - n)/6 per step
-  roofline   the bulk kernel (the dominant one) against the fp64 VALU issue
-             rate: each split evaluation is an fp64 fma, add and min, i.e.
-             3 VALU lane-ops; peak = 256 CUs x 64 lanes x 2.4 GHz.  Its
-             duration is measured with HIP events on the launch streams
-             around every launch of the last timed step.  `traffic` comes from the committed
-             rocprofv3 FETCH_SIZE/WRITE_SIZE summary, and is null when the
-             kernel source changed since it was taken.
-  cpu_baseline  the CPU oracle on a bounded window of the same chain.
+  roofline   the bulk kernel (the dominant one) against the integer-VALU
+             roofline fixed before any tuning: 7 VALU lane-ops per split
+             evaluation (a 24-bit multiply, two 64-bit adds, a 64-bit
+             compare, three selects), peak 256 CUs x 64 lanes x 2.4 GHz =
+             39.3 TOP/s, i.e. 5.62e12 split evaluations/s.  The kernel's own
+             instruction basis (fp64 keys: fma + add + min, 3 lane-ops per
+             evaluation) is reported beside it.  The kernel's duration comes
+             from one solve on the serial schedule (every launch alone on the
+             device, HIP events on the launch stream), so launches that
+             overlap in the timed steps are not counted twice; the whole-step
+             rate on both bases is reported as well.  `traffic` comes from the
+             committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, and is null
+             when the kernel source changed since it was taken.
+  c1, c2     the n = 128 and n = 2048 chains: median latency over 100 solves
+             (HIP events on the stream), and split evaluations/s.
+  batched    4096 chains (n in [16, 512]) in one plan solve vs plain solves.
+  serving    the 20000-request Poisson stream at 0.8 x the measured plain
+             capacity (and at 2 x, and all at once), served vs plain.
+  cpu_baseline  the CPU oracle on a bounded window of the n = 8192 chain on
+             all host threads, and single-threaded on the n = 128 and n = 2048
+             chains.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -35,8 +48,9 @@ if ROOT not in sys.path:
 
 METRIC = "MCM split evals/s at n=8192; batched instances/s + p99 latency vs plain"
 UNIT = "split evals/s"
-PEAK_OPS = 256 * 64 * 2.4e9      # fp64 VALU lane-ops per second
-OPS_PER_EVAL = 3                 # fma + add + min
+PEAK_OPS = 256 * 64 * 2.4e9      # VALU lane-ops per second (int32 and fp64 alike)
+OPS_PER_EVAL = 7                 # integer accounting of a split evaluation, fixed before tuning
+FP64_OPS_PER_EVAL = 3            # the kernels' own fp64-key evaluation: fma + add + min
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bulk_n8192_hbm_traffic.txt")
 TILED_SRC = os.path.join(ROOT, "paper_2008_01938_amd", "csrc", "k_tiled.hip")
 
@@ -45,6 +59,11 @@ WORKLOADS = {
     "mcm_single_n2048": ("single_n2048", "n=2048, dims uniform int32 [1,1024], seed 1"),
     "mcm_single_n128": ("single_n128", "n=128, dims uniform int32 [1,64], seed 0"),
 }
+
+
+def progress(msg: str) -> None:
+    """A progress line on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def source_sha() -> str:
@@ -113,9 +132,11 @@ def host_cpu() -> dict:
     return {"model": model, "logical_cpus": os.cpu_count(), "threads_allowed": host_threads()}
 
 
-def cpu_baseline(p, target_s: float):
+def cpu_baseline(p, target_s: float, workloads=None):
     """Time the oracle on a window p[0:L+1] of the chain, L sized so the
-    run takes about target_s seconds of wall time on all host threads."""
+    run takes about target_s seconds of wall time on all host threads; then
+    single-threaded on the n = 128 chain (median of 1000 fills) and the
+    n = 2048 chain (median of 3 fills)."""
     import oracle
     threads = host_threads()
     n = len(p) - 1
@@ -130,11 +151,68 @@ def cpu_baseline(p, target_s: float):
     oracle.fill(p[:L + 1], threads=threads)
     dt = time.perf_counter() - t0
     evals = (L ** 3 - L) / 6
-    return {"value": evals / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
-            "host": host_cpu(),
-            "sample": f"oracle on the window of the first {L} matrices of the benchmark "
-                      f"chain ({evals:.3g} split evals, {dt:.1f} s wall, OpenMP over the "
-                      f"cells of each diagonal)"}
+    out = {"value": evals / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
+           "host": host_cpu(),
+           "sample": f"oracle on the window of the first {L} matrices of the benchmark "
+                     f"chain ({evals:.3g} split evals, {dt:.1f} s wall, OpenMP over the "
+                     f"cells of each diagonal)"}
+    if workloads is not None:
+        single = {}
+        for name, maker, reps in (("mcm_single_n128", workloads.single_n128, 1000),
+                                  ("mcm_single_n2048", workloads.single_n2048, 3)):
+            q = maker()
+            k = len(q) - 1
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                oracle.fill(q, threads=1)
+                ts.append(time.perf_counter() - t0)
+            med = float(np.median(ts))
+            single[name] = {"n": k, "fills": reps, "median_ms": 1e3 * med,
+                            "split_evals_per_s": (k ** 3 - k) / 6 / med}
+        out["single_thread"] = single
+    return out
+
+
+def bench_small(binding, workloads, torch, name: str, runs: int = 100, warmup: int = 3):
+    """Latency of one chain (device-resident dims, preallocated tables):
+    HIP events on the caller's stream around each solve (the library joins
+    its second stream back into it before returning), median over `runs`;
+    for the path AUTO picks and for the int64 wavefront."""
+    maker, desc = WORKLOADS[name]
+    p = getattr(workloads, maker)()
+    n = len(p) - 1
+    chain = binding.Chain(p)
+    m = torch.empty((n, n), dtype=torch.int64, device="cuda")
+    s = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    evals = (n ** 3 - n) / 6
+    out = {"workload": name, "dims": desc, "n": n,
+           "algo_auto": {binding.ALGO_TILED: "tiled", binding.ALGO_WAVEFRONT: "wavefront"}[
+               binding.select_algo(p)]}
+    for algo in ("auto", "wavefront"):
+        for _ in range(warmup):
+            chain.solve_into(m, s, algo=algo)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(runs)]
+        wall = []
+        for e0, e1 in ev:
+            t0 = time.perf_counter()
+            e0.record()
+            chain.solve_into(m, s, algo=algo)
+            e1.record()
+            e1.synchronize()
+            wall.append(time.perf_counter() - t0)
+        ms = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+        key = "" if algo == "auto" else "wavefront_"
+        out[key + "median_ms"] = float(np.median(ms))
+        out[key + "p10_ms"] = float(np.percentile(ms, 10))
+        out[key + "p90_ms"] = float(np.percentile(ms, 90))
+        out[key + "wall_median_ms"] = 1e3 * float(np.median(wall))
+        out[key + "split_evals_per_s"] = evals / (float(np.median(ms)) / 1e3)
+    out["runs"] = runs
+    chain.close()
+    return out
 
 
 def bench_batched(binding, workloads, torch, reps: int = 3):
@@ -314,49 +392,76 @@ def bench_pipeline(binding, workloads, torch, sizes=(512, 1024)):
     return {"workload": "MCM chains, dims uniform [1, 1024], seed 7", "sizes": out}
 
 
-def bench_serving(binding, workloads, torch, count: int, rate: float):
+def bench_serving(binding, workloads, torch, count: int, load: float):
     """Open-loop Poisson stream (seed 4, n log-uniform in [8, 4096], dims in
-    [1, 1024]): continuous-batching server against plain FIFO solves."""
+    [1, 1024]): continuous-batching server against plain FIFO solves.  The
+    plain saturated capacity C is measured first (every request arriving at
+    once, solved one at a time); the headline runs the stream at load * C,
+    the overload run at 2 C.  The stream's n and dims do not depend on the
+    rate (the gaps are drawn first and scaled by it)."""
     from paper_2008_01938_amd import serve
-    st = workloads.serving_stream(count=count, rate=rate, seed=4)
-    served = serve.run_served(st, mem_budget=24 << 30, max_slots=256).summary()
-    plain = serve.run_plain(st).summary()
-    # Saturation: the same requests all arriving at once; throughput is
-    # requests over the time to finish them all.
+    budget, slots = 24 << 30, 256
     sat = workloads.serving_stream(count=count, rate=1e12, seed=4)
-    sat_served = serve.run_served(sat, mem_budget=24 << 30, max_slots=256).summary()
     sat_plain = serve.run_plain(sat).summary()
-    # Overload: arrivals at twice the plain saturated capacity, where plain
-    # solving cannot keep up (its queue grows for the whole stream).
-    over_rate = 2.0 * sat_plain["requests_per_s"]
+    progress(f"serving: plain capacity {sat_plain['requests_per_s']:.1f}/s")
+    sat_served = serve.run_served(sat, mem_budget=budget, max_slots=slots).summary()
+    progress(f"serving: served saturated {sat_served['requests_per_s']:.1f}/s")
+    cap = sat_plain["requests_per_s"]
+    rate = load * cap
+    st = workloads.serving_stream(count=count, rate=rate, seed=4)
+    served = serve.run_served(st, mem_budget=budget, max_slots=slots).summary()
+    progress(f"serving at {rate:.1f}/s: served p99 {served['p99_ms']:.2f} ms")
+    plain = serve.run_plain(st).summary()
+    progress(f"serving at {rate:.1f}/s: plain p99 {plain['p99_ms']:.2f} ms")
+    over_rate = 2.0 * cap
     over = workloads.serving_stream(count=count, rate=over_rate, seed=4)
-    over_served = serve.run_served(over, mem_budget=24 << 30, max_slots=256).summary()
+    over_served = serve.run_served(over, mem_budget=budget, max_slots=slots).summary()
+    progress(f"serving at {over_rate:.1f}/s: served p99 {over_served['p99_ms']:.2f} ms")
     over_plain = serve.run_plain(over).summary()
-    return {"workload": f"mcm_serving ({count} requests of the seed-4 stream recipe, "
-                        f"Poisson {rate:g}/s, n log-uniform [8,4096], dims [1,1024])",
-            "served": served, "plain": plain,
+    progress(f"serving at {over_rate:.1f}/s: plain p99 {over_plain['p99_ms']:.2f} ms")
+    return {"workload": f"mcm_serving ({count} requests of the seed-4 stream, n log-uniform "
+                        f"[8,4096], dims [1,1024]; Poisson at {load:g} x the plain capacity = "
+                        f"{rate:.1f}/s)",
+            "requests": count, "plain_capacity_per_s": cap, "load_vs_plain_capacity": load,
+            "rate_per_s": rate, "served": served, "plain": plain,
             "p99_speedup_vs_plain": plain["p99_ms"] / served["p99_ms"],
             "p50_speedup_vs_plain": plain["p50_ms"] / served["p50_ms"],
             "saturation": {"served_requests_per_s": sat_served["requests_per_s"],
                            "plain_requests_per_s": sat_plain["requests_per_s"],
                            "speedup_vs_plain": sat_served["requests_per_s"] /
-                           sat_plain["requests_per_s"]},
-            "overload": {"rate_per_s": over_rate, "served": over_served, "plain": over_plain,
+                           sat_plain["requests_per_s"],
+                           "served": sat_served, "plain": sat_plain},
+            "overload": {"rate_per_s": over_rate, "load_vs_plain_capacity": 2.0,
+                         "served": over_served, "plain": over_plain,
                          "p99_speedup_vs_plain": over_plain["p99_ms"] / over_served["p99_ms"]}}
 
 
-def traffic_probe(binding, torch, chain, m, s):
-    """One solve, then a plain device copy of a known size, for counter
-    collection under rocprofv3 --pmc (FETCH_SIZE / WRITE_SIZE)."""
+def counter_probe(binding, workloads, torch, chain, m, s, batched: bool = True):
+    """For rocprofv3 counter runs: one n = 8192 solve on the serial schedule
+    (every launch alone on the device), one plan solve of the 4096-chain
+    batch, then a plain device copy of a known size (the counters' scale)."""
+    binding.profile_enable(True, classes=[], serial=True)
     chain.solve_into(m, s)
     torch.cuda.synchronize()
+    binding.profile_enable(False)
+    if batched:
+        b = workloads.batched_4096()
+        off = binding.table_offsets(b.ns)
+        total = int(off[-1] + int(b.ns[-1]) ** 2)
+        m_all = torch.empty(total, dtype=torch.int64, device="cuda")
+        s_all = torch.empty(total, dtype=torch.int32, device="cuda")
+        plan = binding.Plan(b.ns, b.p_off, off, int(b.p_all.max()))
+        plan.solve_into(b.p_all, m_all, s_all)
+        torch.cuda.synchronize()
+        plan.close()
+        del m_all, s_all
     nbytes = 1 << 30
     src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"traffic_probe": True, "copy_bytes": nbytes,
+    print(json.dumps({"counter_probe": True, "copy_bytes": nbytes, "batched": batched,
                       "kernel_source_sha256": source_sha()}), flush=True)
 
 
@@ -369,16 +474,19 @@ def main() -> int:
     ap.add_argument("--algo", default="auto", choices=["auto", "tiled", "wavefront"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall time target of the CPU-baseline sample (0 = skip)")
-    ap.add_argument("--traffic-probe", action="store_true",
-                    help="one solve plus a 1 GiB copy, for rocprofv3 --pmc runs")
+    ap.add_argument("--counter-probe", action="store_true",
+                    help="one serial-schedule solve, one batched plan solve and a 1 GiB "
+                         "copy, for rocprofv3 counter runs")
+    ap.add_argument("--no-small", action="store_true", help="skip the n=128 / n=2048 section")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--no-sdp", action="store_true", help="skip the S-DP section")
     ap.add_argument("--no-obst", action="store_true", help="skip the optimal-BST section")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the pipeline (Fig. 8) ablation section")
-    ap.add_argument("--serve-requests", type=int, default=1000)
-    ap.add_argument("--serve-rate", type=float, default=600.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="arrival rate as a multiple of the measured plain capacity")
     args = ap.parse_args()
 
     if args.steps < 1 or args.warmup < 0:
@@ -412,64 +520,77 @@ def main() -> int:
     s = torch.empty((n, n), dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
 
-    if args.traffic_probe:
-        traffic_probe(binding, torch, chain, m, s)
+    if args.counter_probe:
+        counter_probe(binding, workloads, torch, chain, m, s, batched=not args.no_batched)
         return 0
 
     for _ in range(args.warmup):
         chain.solve_into(m, s, algo=algo)
     torch.cuda.synchronize()
 
-    # The last timed step marks the dominant kernel's launches with events
-    # (every marked launch adds two event records to its stream, so marking
-    # every step would tax the throughput being measured).
-    dom = "bulk" if chosen == "tiled" else "wavefront"
-    dom_class = binding.PROF_BULK if dom == "bulk" else binding.PROF_WAVE
+    # The timed steps carry no profiling events.
     binding.profile_enable(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for step in range(args.steps):
-        if step == args.steps - 1:
-            binding.profile_enable(True, classes=[dom_class])
+    for _ in range(args.steps):
         chain.solve_into(m, s, algo=algo)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    d = binding.profile_read(dom_class)
-    binding.profile_enable(False)
 
-    # Per-class kernel time from one more solve with every class marked.
+    # Per-class kernel time from one more solve with every class marked, on
+    # the benchmark's own (overlapped) schedule: launches of different
+    # classes run at once, so the classes' sums exceed the step.
+    names = ["setup", "bulk", "close", "wavefront", "batched"]
     binding.profile_enable(True)
     chain.solve_into(m, s, algo=algo)
     torch.cuda.synchronize()
-    prof = {name: binding.profile_read(c) for c, name in
-            enumerate(["setup", "bulk", "close", "wavefront", "batched"])}
+    prof = {name: binding.profile_read(c) for c, name in enumerate(names)}
+    binding.profile_enable(False)
+    # The same solve on the serial schedule: every launch alone on the
+    # device, so each class's event-timed duration is the kernel's own.
+    binding.profile_enable(True, serial=True)
+    ts0 = time.perf_counter()
+    chain.solve_into(m, s, algo=algo)
+    torch.cuda.synchronize()
+    serial_wall = time.perf_counter() - ts0
+    prof_serial = {name: binding.profile_read(c) for c, name in enumerate(names)}
     binding.profile_enable(False)
 
     elapsed = t1 - t0
     evals = (n ** 3 - n) / 6
     value = evals * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
+    dom = "bulk" if chosen == "tiled" else "wavefront"
+    d = prof_serial[dom]
     avg_s = d["ms"] / 1e3 / max(1, d["launches"])
-    evals_per_launch = d["split_evals"] / max(1, d["launches"])
-    achieved = evals_per_launch * OPS_PER_EVAL / avg_s if avg_s > 0 else 0.0
+    rate = d["split_evals"] / (d["ms"] / 1e3) if d["ms"] > 0 else 0.0
     traffic = read_traffic() if chosen == "tiled" and args.workload == "mcm_single_n8192" else None
     roofline = {
         "bound": "alu",
-        "achieved": round(achieved / 1e12, 4),
+        "achieved": round(rate * OPS_PER_EVAL / 1e12, 4),
         "peak": round(PEAK_OPS / 1e12, 4),
         "unit": "TOP/s",
-        "frac": round(achieved / PEAK_OPS, 4),
+        "frac": round(rate * OPS_PER_EVAL / PEAK_OPS, 4),
         "traffic": traffic,
         "kernel": "k_bulk" if dom == "bulk" else "k_wave_diag",
+        "basis": "7 int32-VALU lane-ops per split evaluation (fixed before tuning); "
+                 "peak 256 CUs x 64 lanes x 2.4 GHz",
         "ops_per_split_eval": OPS_PER_EVAL,
+        "kernel_split_evals_per_s": rate,
         "avg_launch_ms": round(avg_s * 1e3, 5),
-        "launches_per_step": d["launches"],
+        "launches_per_solve": d["launches"],
+        "split_evals_per_launch": d["split_evals"] / max(1, d["launches"]),
+        "duration_source": "HIP events around each launch of one solve on the serial schedule",
+        "frac_fp64_issue": round(rate * FP64_OPS_PER_EVAL / PEAK_OPS, 4),
+        "step_frac": round(value * OPS_PER_EVAL / PEAK_OPS, 4),
+        "step_frac_fp64_issue": round(value * FP64_OPS_PER_EVAL / PEAK_OPS, 4),
     }
     sclk = read_sclk() if dom == "bulk" else None
     if sclk:
-        # The same fraction against the clock measured while k_bulk runs.
+        # The fp64-issue fraction against the clock measured while k_bulk runs.
         roofline["sclk_ghz_measured"] = sclk
-        roofline["frac_at_measured_sclk"] = round(achieved / (256 * 64 * sclk * 1e9), 4)
+        roofline["frac_fp64_issue_at_measured_sclk"] = round(
+            rate * FP64_OPS_PER_EVAL / (256 * 64 * sclk * 1e9), 4)
 
     out = {
         "metric": METRIC,
@@ -488,7 +609,10 @@ def main() -> int:
                    "exact_integer": True, "parallelism": "single GPU"},
         "roofline": roofline,
         "kernels_ms_per_step": {k: round(v["ms"], 4) for k, v in prof.items()},
+        "kernels_ms_serial": {k: round(v["ms"], 4) for k, v in prof_serial.items()},
+        "serial_solve_ms": round(1e3 * serial_wall, 3),
     }
+    progress(f"n={n}: {ms_per_step:.3f} ms per step; serial solve {1e3 * serial_wall:.2f} ms")
     rec = bench_reconstruction(binding, torch, p, m, s)
     rec["solve_fraction"] = round(rec["tree_cost_text_ms"] / ms_per_step, 4)
     out["reconstruction"] = rec
@@ -496,19 +620,27 @@ def main() -> int:
     del m, s
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    if not args.no_small:
+        out["c1"] = bench_small(binding, workloads, torch, "mcm_single_n128")
+        out["c2"] = bench_small(binding, workloads, torch, "mcm_single_n2048")
+        progress(f"n=128 {out['c1']['median_ms']:.3f} ms, n=2048 {out['c2']['median_ms']:.3f} ms")
     if not args.no_batched:
         out["batched"] = bench_batched(binding, workloads, torch)
+        progress(f"batched {out['batched']['ms']:.2f} ms")
     if not args.no_serving:
         out["serving"] = bench_serving(binding, workloads, torch, args.serve_requests,
-                                       args.serve_rate)
+                                       args.serve_load)
     if not args.no_sdp:
         out["sdp"] = bench_sdp(binding, workloads, torch)
+        progress("sdp done")
     if not args.no_obst:
         out["obst"] = bench_obst(binding, torch)
+        progress("obst done")
     if not args.no_pipeline:
         out["pipeline_ablation"] = bench_pipeline(binding, workloads, torch)
+        progress("pipeline ablation done")
     if args.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds, workloads)
     print(json.dumps(out), flush=True)
     return 0
 

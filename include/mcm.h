@@ -139,7 +139,7 @@ mcm_status mcm_solve_algo(const int32_t *p, int32_t n, int64_t *m_out, int32_t *
  *   tab_off host, count entries: chain b's m table is m_all + tab_off[b]
  *           and its s table s_all + tab_off[b], n[b]*n[b] elements each,
  *           row-major, same contract as mcm_solve; tables of different
- *           chains must not overlap.
+ *           chains must not overlap (checked: MCM_ERR_INVALID_ARG).
  *   m_all, s_all  device buffers (int64 / int32), caller-owned.
  * Every chain is validated before anything is enqueued; the first failure
  * is returned and nothing runs.
@@ -252,7 +252,7 @@ void mcm_chain_destroy(mcm_chain *chain, hipStream_t stream);
  *     tab_off   host: chain b's split table is s_all + tab_off[b] (n*n).
  *     node_off  host: chain b's products are lo_all/hi_all + node_off[b]
  *               (n[b]-1 entries each; ranges of different chains must not
- *               overlap).
+ *               overlap: checked, MCM_ERR_INVALID_ARG).
  *     cost_all  device, count int64, or NULL: per-chain tree cost, needing
  *               p_off/p_all (host, as in mcm_solve_batched).
  *   Same invalid-table behaviour per chain.  All chains are validated
@@ -351,9 +351,13 @@ mcm_status mcm_obst_solve_algo(const int32_t *p, const int32_t *q, int32_t n, in
  *                      the arena cannot be allocated.
  *   mcm_server_submit  validates p (host, n+1 dims, copied before return)
  *                      and queues the request under the caller's `tag`.
- *                      MCM_ERR_INVALID_ARG / MCM_ERR_OVERFLOW for a bad
- *                      chain, MCM_ERR_NO_MEMORY if the request alone
- *                      exceeds the arena; never blocks.
+ *                      A tag names one request from its submission until
+ *                      its release: submitting under a live tag returns
+ *                      MCM_ERR_INVALID_ARG.  MCM_ERR_INVALID_ARG /
+ *                      MCM_ERR_OVERFLOW for a bad chain, MCM_ERR_NO_MEMORY
+ *                      if the request alone exceeds the arena; never
+ *                      blocks (the queue is unbounded, so admission
+ *                      failure is a wait in the queue, not an error).
  *   mcm_server_poll    moves up to `cap` completed requests into `out`
  *                      (oldest first) and sets *count.  m and s are device
  *                      pointers into the arena, valid until released.
@@ -405,7 +409,14 @@ double mcm_clock_now(void);
 void mcm_profile_enable(int32_t on);
 /* Times only the classes whose bit is set (bit c: class c); 0 disables.
  * Each timed launch adds two event records to its stream, so a caller that
- * times one kernel class can leave the others unmarked. */
+ * times one kernel class can leave the others unmarked.
+ * MCM_PROFILE_SERIAL in the mask (with or without class bits) runs every
+ * single-chain tiled solve as a serial schedule while it is set: every
+ * launch on the caller's stream in schedule order, the bulk chunking fitted
+ * to the whole device, so each timed launch has the device to itself and
+ * its duration is the kernel's alone.  The bytes written are the same; the
+ * solve is slower (nothing overlaps). */
+#define MCM_PROFILE_SERIAL (1u << 16)
 void mcm_profile_enable_mask(uint32_t mask);
 mcm_status mcm_profile_read(int32_t kernel_class, double *total_ms, int64_t *launches,
                             double *split_evals);

@@ -30,6 +30,7 @@ ALGOS = {"auto": ALGO_AUTO, "wavefront": ALGO_WAVEFRONT, "tiled": ALGO_TILED,
 
 # Profiler kernel classes (mcm_profile_read).
 PROF_SETUP, PROF_BULK, PROF_CLOSE, PROF_WAVE, PROF_BATCH = range(5)
+PROFILE_SERIAL = 1 << 16   # MCM_PROFILE_SERIAL
 
 # Every symbol include/mcm.h declares.
 EXPORTED = (
@@ -616,15 +617,19 @@ class Server:
         self.close()
 
 
-def profile_enable(on: bool = True, classes=None) -> None:
-    """Time every kernel class (or only those listed in `classes`)."""
-    if classes is None:
+def profile_enable(on: bool = True, classes=None, serial: bool = False) -> None:
+    """Time every kernel class (or only those listed in `classes`).
+    serial: single-chain tiled solves run the serial schedule meanwhile
+    (MCM_PROFILE_SERIAL), so each timed launch has the device alone."""
+    if classes is None and not serial:
         load().mcm_profile_enable(1 if on else 0)
-    else:
-        mask = 0
-        for c in classes:
-            mask |= 1 << int(c)
-        load().mcm_profile_enable_mask(mask if on else 0)
+        return
+    mask = 0
+    for c in (range(5) if classes is None else classes):
+        mask |= 1 << int(c)
+    if serial:
+        mask |= PROFILE_SERIAL
+    load().mcm_profile_enable_mask(mask if on else 0)
 
 
 def profile_read(kernel_class: int) -> dict:

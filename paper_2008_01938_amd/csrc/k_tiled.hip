@@ -838,7 +838,8 @@ double wave_cost(int64_t units, int32_t ks, int64_t slots)
 
 }  // namespace
 
-BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus, int slots_per_cu)
+BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus, int slots_per_cu,
+                       bool serial)
 {
     BulkLayout bl{};
     if (E < 2 || E >= NT) return bl;
@@ -847,7 +848,10 @@ BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus, in
     cap = cap / KC * KC;
     const bool fit = lone && cus >= 64 && slots_per_cu > 0;
     int64_t slots_int = 0, slots_end = 0;
-    if (fit) {
+    if (fit && serial) {
+        // Serial schedule: every launch has the whole device.
+        slots_int = slots_end = (int64_t)slots_per_cu * cus;
+    } else if (fit) {
         // The closure of E-1 holds one CU per tile (NT-E+1) while the
         // interior runs; the end blocks follow the closure on those CUs.
         int64_t held = NT - E + 1;
@@ -896,7 +900,7 @@ BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus, in
         bl.int_ks = ks;
         bl.int_nch = (L + ks - 1) / ks;
         bl.int_len = L;
-        if (fit) {
+        if (fit && !serial) {
             // Alternative: one wave of long chunks on the interior's slots,
             // then one wave of short chunks that start on the closure's CUs
             // once the closure is done (it takes about kCloseSplits split
@@ -1131,7 +1135,8 @@ void plan_lockstep(TiledPlan &plan, const std::vector<int> &ids)
         if (v.empty()) {
             v.resize((size_t)NT + 1);
             for (int E = 0; E <= NT; ++E)
-                v[E] = bulk_layout(NT, E, kb, plan.lone, plan.cus, plan.slots_per_cu);
+                v[E] = bulk_layout(NT, E, kb, plan.lone, plan.cus, plan.slots_per_cu,
+                                   plan.serial);
         }
         return v;
     };
@@ -1311,16 +1316,32 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
     return st;
 }
 
+// The serial schedule: the plan's launch order already respects every
+// dependency (each launch follows everything it waits for), so one stream
+// runs it as is.
+static void plan_make_serial(TiledPlan &plan)
+{
+    for (TiledLaunch &L : plan.launches) {
+        L.stream = 0;
+        L.wait = -1;
+        L.record = false;
+    }
+    plan.uses_aux = false;
+    plan.last_interior = -1;
+}
+
 mcm_status run_tiled(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int32_t *s,
                      hipStream_t stream)
 {
     if (!tiled_accepts(ci)) return MCM_ERR_UNSUPPORTED;
     TiledPlan plan;
     plan.lone = true;
+    plan.serial = profile_serial();
     plan.cus = device_cus();
     plan.slots_per_cu = bulk_blocks_per_cu();
     const int c = plan_add_chain(plan, ci, 0, 0, 0, 0);
     plan_lockstep(plan, {c});
+    if (plan.serial) plan_make_serial(plan);
     return run_tiled_plan(plan, dc.p, dc.pd, m, s, nullptr, stream, nullptr);
 }
 

@@ -3,6 +3,7 @@
 // before making any HIP call, so invalid input never touches the device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <memory>
 #include <mutex>
@@ -45,6 +46,20 @@ mcm_status chain_bound(int32_t n, int32_t pmax, ChainInfo *ci)
         ci->cost_bits = bits;
     }
     return MCM_OK;
+}
+
+bool ranges_disjoint(int32_t count, const int32_t *n, const int64_t *off, bool square)
+{
+    std::vector<std::pair<int64_t, int64_t>> r;
+    r.reserve((size_t)count);
+    for (int32_t b = 0; b < count; ++b) {
+        const int64_t len = square ? (int64_t)n[b] * n[b] : (int64_t)n[b] - 1;
+        if (len > 0) r.emplace_back(off[b], off[b] + len);
+    }
+    std::sort(r.begin(), r.end());
+    for (size_t u = 1; u < r.size(); ++u)
+        if (r[u].first < r[u - 1].second) return false;
+    return true;
 }
 
 namespace {
@@ -128,6 +143,7 @@ struct ProfRecord {
     double evals;
 };
 std::atomic<uint32_t> g_prof_mask{0};  // bit c: kernel class c is timed
+std::atomic<bool> g_prof_serial{false};  // MCM_PROFILE_SERIAL
 std::mutex g_prof_mu;
 std::vector<ProfRecord> g_prof_pending;
 std::vector<hipEvent_t> g_prof_free;  // recycled events (creation is a host cost per launch)
@@ -368,6 +384,8 @@ void ws_free(void *ptr, hipStream_t stream)
     if (ptr) (void)hipFreeAsync(ptr, stream);
 }
 
+bool profile_serial() { return g_prof_serial.load(std::memory_order_relaxed); }
+
 ProfileScope::ProfileScope(int cls, hipStream_t stream, double evals)
     : cls_(cls), stream_(stream), evals_(evals)
 {
@@ -512,6 +530,8 @@ mcm_status mcm_solve_batched(int32_t count, const int32_t *n, const int64_t *p_o
         if (st != MCM_OK) return st;
         if (p_off[b] + n[b] + 1 > p_len) p_len = p_off[b] + n[b] + 1;
     }
+    // Overlapping tables would race between concurrent tiles.
+    if (!ranges_disjoint(count, n, tab_off, true)) return MCM_ERR_INVALID_ARG;
     if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
 
     // All dims in one upload of p_len int32 (padded to 8 bytes); their fp64
@@ -582,6 +602,7 @@ mcm_status mcm_plan_create(int32_t count, const int32_t *n, const int64_t *p_off
         if (st != MCM_OK) return st;
         if (p_off[b] + n[b] + 1 > pl->p_len) pl->p_len = p_off[b] + n[b] + 1;
     }
+    if (!ranges_disjoint(count, n, tab_off, true)) return MCM_ERR_INVALID_ARG;
     if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
     if (hipGetDevice(&pl->device) != hipSuccess) return MCM_ERR_DEVICE;
     std::vector<int> ids;
@@ -783,9 +804,13 @@ void mcm_profile_enable_mask(uint32_t mask)
     std::lock_guard<std::mutex> lk(g_prof_mu);
     prof_clear_locked();
     g_prof_mask.store(mask & ((1u << KC_COUNT) - 1u));
+    g_prof_serial.store((mask & MCM_PROFILE_SERIAL) != 0);
 }
 
-void mcm_profile_enable(int32_t on) { mcm_profile_enable_mask(on ? ~0u : 0u); }
+void mcm_profile_enable(int32_t on)
+{
+    mcm_profile_enable_mask(on ? (1u << KC_COUNT) - 1u : 0u);
+}
 
 mcm_status mcm_profile_read(int32_t kernel_class, double *total_ms, int64_t *launches,
                             double *split_evals)

@@ -34,6 +34,10 @@ struct ProfileScope {
     hipEvent_t start_ = nullptr;
 };
 
+// True while MCM_PROFILE_SERIAL is set: single-chain tiled solves use the
+// serial schedule (one stream, chunking fitted to the whole device).
+bool profile_serial();
+
 // Device copies of the chain, in the forms the kernels read.
 struct DeviceChain {
     const int32_t *p = nullptr;   // n+1 int32
@@ -44,6 +48,10 @@ struct DeviceChain {
 mcm_status check_chain(const int32_t *p, int32_t n, ChainInfo *ci);
 // The facts of any chain of n matrices whose dims are at most pmax.
 mcm_status chain_bound(int32_t n, int32_t pmax, ChainInfo *ci);
+// True when the ranges [off[b], off[b] + len(b)) of the `count` entries are
+// pairwise disjoint (len(b) = n[b]^2 when square, else n[b] - 1); entries
+// with an empty range never conflict.  Host only.
+bool ranges_disjoint(int32_t count, const int32_t *n, const int64_t *off, bool square);
 
 // Enqueue a copy of `bytes` host bytes, written by `fill` into pinned
 // staging memory, to the existing device buffer `dst` on `stream`.
@@ -252,6 +260,7 @@ struct TiledPlan {
     std::vector<TiledLaunch> launches;
     size_t part_elems = 0;             // partial-minima buffer (uint64) the plan needs
     bool lone = false;                 // one chain: fit bulk chunks to the GPU's slots
+    bool serial = false;               // lone: one stream, chunks fitted to the whole device
     int cus = 0;                       // lone: compute units of the device
     int slots_per_cu = 0;              // lone: resident k_bulk workgroups per CU
     int pair_min_blocks = 0;           // closures with more workgroups use the paired
@@ -276,8 +285,9 @@ struct ChainStep {
 
 int32_t tiled_nt(int32_t n);
 // lone: cus / slots_per_cu describe the device (TiledPlan); else ignored.
+// serial: the launches run alone on the device (every CU free).
 BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus = 0,
-                       int slots_per_cu = 0);
+                       int slots_per_cu = 0, bool serial = false);
 // Interior cut into `nch` chunks per tile (clamped to [1, kMaxChunks] and
 // to chunks of at least 64 splits), end blocks in chunks of 64 splits.
 BulkLayout bulk_layout_chunks(int32_t NT, int32_t E, int32_t kb, int32_t nch);

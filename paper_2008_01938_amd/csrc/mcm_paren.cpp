@@ -125,6 +125,8 @@ mcm_status mcm_parenthesize_batched(int32_t count, const int32_t *n, const int64
         q_len += n[b] > 1 ? n[b] - 1 : 0;
         if (n[b] > max_n) max_n = n[b];
     }
+    // Overlapping node ranges would be written by two workgroups at once.
+    if (!ranges_disjoint(count, n, node_off, false)) return MCM_ERR_INVALID_ARG;
     if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
 
     Workspace ws(stream);

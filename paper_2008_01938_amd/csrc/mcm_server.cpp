@@ -19,6 +19,7 @@
 #include <string.h>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "mcm_internal.h"
@@ -135,6 +136,7 @@ struct Server {
     std::deque<Inflight> inflight;                   // enqueued iterations
     std::deque<Request *> done;                      // complete, not yet polled
     std::unordered_map<uint64_t, Request *> polled;  // polled, not yet released
+    std::unordered_set<uint64_t> live;               // tags submitted, not yet released
     int64_t slots_used = 0, completed = 0, iterations = 0;
     bool stop = false;
     std::thread th;
@@ -374,9 +376,15 @@ mcm_status mcm_server_submit(mcm_server *srv, const int32_t *p, int32_t n, uint6
         delete r;
         return MCM_ERR_NO_MEMORY;
     }
-    r->t_submit = now_s();
     {
         std::lock_guard<std::mutex> lk(srv->mu);
+        // A tag names one request until it is released: a second request
+        // under a live tag could never be released on its own.
+        if (!srv->live.insert(tag).second) {
+            delete r;
+            return MCM_ERR_INVALID_ARG;
+        }
+        r->t_submit = now_s();
         srv->queue.push_back(r);
     }
     srv->cv.notify_all();
@@ -429,6 +437,7 @@ mcm_status mcm_server_release(mcm_server *srv, uint64_t tag)
         if (it == srv->polled.end()) return MCM_ERR_INVALID_ARG;
         r = it->second;
         srv->polled.erase(it);
+        srv->live.erase(tag);
         srv->arena.release(r->off, r->bytes);
         srv->slots_used -= 1;
     }

@@ -16,3 +16,15 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs a gfx950 GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running case")
+
+
+@pytest.fixture(scope="session")
+def n8192_oracle():
+    """The oracle's whole tables for the n = 8192 benchmark chain (dims
+    uniform in [1, 1024], seed 2), filled once on every host thread."""
+    import oracle
+    from paper_2008_01938_amd import workloads
+    p = workloads.single_n8192()
+    print("[cpu] oracle fill n=8192 on all host threads", flush=True)
+    m, s = oracle.fill(p, threads=oracle.default_threads())
+    return p, m, s

@@ -141,6 +141,11 @@ def test_batched_rejects_bad_input_before_device(lib):
     assert call([2], [0], [1 << 21] * 3, [0]) == binding.ERR_OVERFLOW
     assert call([2], [0], [3, 4, 5], [0], count=-1) == binding.ERR_INVALID_ARG
     assert call([], [], [], [], count=0) == binding.OK                             # no-op
+    # Tables that overlap would race between concurrent tiles: chain 1's
+    # 2x2 table at offset 3 overlaps chain 0's [0, 4); in either order.
+    assert call([2, 2], [0, 0], [3, 4, 5], [0, 3]) == binding.ERR_INVALID_ARG
+    assert call([2, 2], [0, 0], [3, 4, 5], [3, 0]) == binding.ERR_INVALID_ARG
+    assert call([3, 2, 1], [0, 0, 0], [3, 4, 5, 6], [20, 0, 3]) == binding.ERR_INVALID_ARG
     assert np.all(m == 7) and np.all(s == 7)
 
 
@@ -165,6 +170,7 @@ def test_plan_rejects_bad_input_before_device(lib):
     assert create([2], [0], [0], 0) == binding.ERR_INVALID_ARG                # max_dim
     assert create([2], [0], [0], 1 << 21) == binding.ERR_OVERFLOW             # 1 * (2^21)^3
     assert create([2], [0], [0], 8, count=-1) == binding.ERR_INVALID_ARG
+    assert create([2, 2], [0, 0], [0, 2], 8) == binding.ERR_INVALID_ARG       # tables overlap
     p = np.array([3, 4, 5], dtype=np.int32)
     m = np.zeros(4, dtype=np.int64)
     s = np.zeros(4, dtype=np.int32)
@@ -221,6 +227,16 @@ def test_parenthesize_rejects_bad_input_before_device(lib):
     assert g(2, ns.ctypes.data_as(i32), None, None, off.ctypes.data_as(i64), vp(s.ctypes.data),
              off.ctypes.data_as(i64), vp(lo.ctypes.data), vp(lo.ctypes.data), None,
              None) == binding.ERR_INVALID_ARG
+    # node ranges [0, 3) and [2, 5) overlap (the split tables do not)
+    ns2 = np.array([4, 4], dtype=np.int32)
+    toff = np.array([0, 16], dtype=np.int64)
+    noff = np.array([0, 2], dtype=np.int64)
+    s2 = np.full(32, 7, dtype=np.int32)
+    lo2 = np.full(8, 7, dtype=np.int32)
+    assert g(2, ns2.ctypes.data_as(i32), None, None, toff.ctypes.data_as(i64),
+             vp(s2.ctypes.data), noff.ctypes.data_as(i64), vp(lo2.ctypes.data),
+             vp(lo2.ctypes.data), None, None) == binding.ERR_INVALID_ARG
+    assert (s2 == 7).all() and (lo2 == 7).all()
 
 
 def test_sdp_rejects_bad_input_before_device(lib):

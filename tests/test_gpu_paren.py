@@ -178,38 +178,21 @@ def test_batched_workload_end_to_end():
         assert cost[b] == ocost
 
 
-def test_benchmark_chain_full_size():
-    # n = 8192: the oracle's fill is too slow here, so the tree the GPU reads
-    # back from the GPU's own table is checked by properties that pin it:
-    # every product k sits at a cell whose split is k, the root spans the
-    # chain, the children of every product are products or matrices of the
-    # right span, its cost equals the solved m[0][n-1], and the text parses
-    # to the same tree.
+def test_benchmark_chain_full_size(n8192_oracle):
+    # n = 8192, the benchmark chain: the tree the GPU reads back from the
+    # GPU's own table equals the oracle's read-back of the oracle's table
+    # (intervals, cost and text), and its cost equals the solved m[0][n-1].
     import torch
-    p = workloads.single_n8192()
+    p, om, os_ = n8192_oracle
     n = len(p) - 1
     _say(f"[gpu] solve + parenthesize n={n}")
     m, s = binding.solve(p, algo="tiled")
     lo, hi, cost, text = binding.parenthesize(s, p=p)
     torch.cuda.synchronize()
-    lo, hi = lo.cpu().numpy().astype(np.int64), hi.cpu().numpy().astype(np.int64)
-    k = np.arange(n - 1)
-    s_at = s.view(-1)[torch.as_tensor(lo * n + hi, device="cuda")].cpu().numpy()
-    assert np.array_equal(s_at, k), "a product is not at a cell with its split"
-    assert np.all(lo <= k) and np.all(k < hi)
-    root = np.flatnonzero((lo == 0) & (hi == n - 1))
-    assert root.size == 1
-    # left child of k spans lo..k: a matrix (lo == k) or the product at
-    # s[lo][k], whose interval must be exactly lo..k; same on the right.
-    left = s.view(-1)[torch.as_tensor(lo * n + k, device="cuda")].cpu().numpy().astype(np.int64)
-    inner = lo < k
-    assert np.all(lo[left[inner]] == lo[inner]) and np.all(hi[left[inner]] == k[inner])
-    right = s.view(-1)[torch.as_tensor((k + 1) * n + hi, device="cuda")].cpu().numpy()
-    right = right.astype(np.int64)
-    inner = k + 1 < hi
-    assert np.all(lo[right[inner]] == k[inner] + 1) and np.all(hi[right[inner]] == hi[inner])
-    pl = p.astype(np.int64)
-    assert cost == int(np.sum(pl[lo] * pl[k + 1] * pl[hi + 1])) == int(m[0, n - 1].item())
+    lo, hi = lo.cpu().numpy(), hi.cpu().numpy()
+    _say("[cpu] oracle read-back n=8192")
+    olo, ohi, ocost, otext = paren.reconstruct(p, os_)
+    assert np.array_equal(lo, olo) and np.array_equal(hi, ohi)
+    assert cost == ocost == int(om[0, n - 1]) == int(m[0, n - 1].item())
+    assert text == otext
     assert len(text) == binding.parens_length(n)
-    depth = np.cumsum([1 if c == "(" else -1 if c == ")" else 0 for c in text])
-    assert depth.min() >= 0 and depth[-1] == 0

@@ -2,8 +2,11 @@
 
 Every case prints its name, shape and kernel path before touching the GPU
 so a failing run can be attributed.  Whole n x n buffers are compared
-wherever the oracle can fill the table in seconds; at n = 8192 the check
-uses sampled cells, oracle windows and properties that hold at any size.
+wherever the oracle can fill the table in seconds on the host's threads,
+which includes the n = 8192 benchmark chain.  Beyond that (n = 16384, where
+the bulk kernel stages with 64-bit offsets) the check uses oracle windows,
+a large sample of cells re-evaluated from the table, and the closed form of
+all-equal dimensions over the whole table.
 """
 import sys
 
@@ -125,6 +128,29 @@ def test_profile_counts_every_split():
         assert total == (n ** 3 - n) // 6, (algo, total)
 
 
+def test_serial_profile_schedule_same_bytes():
+    # The profiler's serial schedule (every launch on the caller's stream,
+    # chunking fitted to the whole device) writes the same bytes and still
+    # counts every split; switching it off restores the overlapped schedule.
+    import torch
+    p = workloads.uniform_dims(1500, 1, 1024, 1500)
+    n = len(p) - 1
+    binding.profile_enable(True, serial=True)
+    try:
+        m, s = gpu_solve(p, "tiled")
+        torch.cuda.synchronize()
+        total = sum(binding.profile_read(c)["split_evals"] for c in range(5))
+        bulk = binding.profile_read(binding.PROF_BULK)
+    finally:
+        binding.profile_enable(False)
+    assert total == (n ** 3 - n) // 6
+    assert bulk["launches"] > 0 and bulk["ms"] > 0
+    om, os_ = oracle.fill(p, threads=oracle.default_threads())
+    assert np.array_equal(m, om) and np.array_equal(s, os_)
+    m2, s2 = gpu_solve(p, "tiled")
+    assert np.array_equal(m2, om) and np.array_equal(s2, os_)
+
+
 def test_nondefault_stream_and_repeat_determinism():
     import torch
     p = workloads.uniform_dims(700, 1, 1024, 123)
@@ -152,6 +178,19 @@ def n8192():
     assert binding.select_algo(p) == binding.ALGO_TILED
     m, s = gpu_solve(p, "auto")
     return p, m, s
+
+
+def test_n8192_whole_table_matches_oracle(n8192, n8192_oracle):
+    # Every cell of both n x n buffers, against the oracle's own fill.
+    p, m, s = n8192
+    op, om, os_ = n8192_oracle
+    assert np.array_equal(p, op)
+    for name, got, want in (("m", m, om), ("s", s, os_)):
+        if not np.array_equal(got, want):
+            bad = np.argwhere(got != want)
+            i, j = bad[0]
+            raise AssertionError(f"{name} differs at {len(bad)} cells, first ({i},{j}): "
+                                 f"gpu {got[i, j]} oracle {want[i, j]}")
 
 
 def test_n8192_structure(n8192):
@@ -227,3 +266,72 @@ def test_chain_api_matches_solve():
         assert np.array_equal(m.cpu().numpy(), om) and np.array_equal(s.cpu().numpy(), os_)
     ch.close()
     torch.cuda.synchronize()
+
+
+# --------------------------------------------------------------------------
+# n = 16384: the table passes 2 GiB, so the bulk kernel stages its panels
+# with 64-bit offsets instead of 32-bit ones.
+# --------------------------------------------------------------------------
+
+def _device_closed_form(n, d):
+    """Whole-table check of the all-equal closed form on the device:
+    m[i][j] = |j - i| d^3 and s[i][j] = i above the diagonal, -1 elsewhere."""
+    import torch
+    p = workloads.all_equal(n, d)
+    _say(f"[gpu] solve n={n} all dims {d} (closed form)")
+    m, s = binding.solve(p, algo="auto")
+    torch.cuda.synchronize()
+    ar = torch.arange(n, device="cuda", dtype=torch.int64)
+    for r0 in range(0, n, 2048):   # row blocks keep the expected tables small
+        r = ar[r0:r0 + 2048, None]
+        want_m = (ar[None, :] - r).abs() * (d ** 3)
+        want_s = torch.where(ar[None, :] > r, r, torch.full_like(r, -1)).to(torch.int32)
+        assert torch.equal(m[r0:r0 + 2048], want_m), f"m rows {r0}.."
+        assert torch.equal(s[r0:r0 + 2048], want_s), f"s rows {r0}.."
+    return m, s
+
+
+def test_n16384_all_equal_closed_form():
+    n, d = 16384, 1024
+    assert binding.select_algo(workloads.all_equal(n, d)) == binding.ALGO_TILED
+    m, s = _device_closed_form(n, d)
+    assert int(m[0, n - 1].item()) == (n - 1) * d ** 3
+    del m, s
+
+
+def test_n16384_random_dims_windows_and_cells():
+    # Random dims at n = 16384: oracle windows (optimal substructure makes
+    # a window's table a block of the full one) at both ends and inside,
+    # plus 10^6 cells spread over every distance class re-evaluated from
+    # the table itself, including the full chain.
+    import torch
+    n = 16384
+    p = workloads.uniform_dims(n, 1, 1024, 16384)
+    assert binding.select_algo(p) == binding.ALGO_TILED
+    _say(f"[gpu] solve n={n} random dims")
+    mt, st = binding.solve(p, algo="auto")
+    torch.cuda.synchronize()
+    m, s = mt.cpu().numpy(), st.cpu().numpy()
+    del mt, st
+    thr = oracle.default_threads()
+    rng = np.random.default_rng(16384)
+    L = 700
+    for i0 in [0, n - L] + [int(x) for x in rng.integers(0, n - L, size=3)]:
+        _say(f"[cpu] oracle window i0={i0} L={L}")
+        wm, ws = oracle.fill(p[i0:i0 + L + 1], threads=thr)
+        assert np.array_equal(m[i0:i0 + L, i0:i0 + L], wm), f"window {i0}: m"
+        assert np.array_equal(s[i0:i0 + L, i0:i0 + L], np.where(ws >= 0, ws + i0, -1)), \
+            f"window {i0}: s"
+    i = rng.integers(0, n - 1, size=1_000_000)
+    d = np.maximum(np.minimum(rng.integers(1, n, size=i.size), n - 1 - i), 1)
+    cells = np.stack([i, i + d], axis=1)
+    cells = np.concatenate([cells, [[0, n - 1], [1, n - 1], [0, n - 2]]])
+    _say(f"[cpu] recurrence at {len(cells)} cells")
+    assert oracle.check_cells(p, m, s, cells, threads=thr) == 0
+    assert np.all(np.diag(m) == 0)
+    ar = np.arange(n)
+    for r0 in range(0, n, 1024):   # row blocks: symmetry, and s = -1 on and below the diagonal
+        rows = slice(r0, r0 + 1024)
+        assert np.array_equal(m[rows], m[:, rows].T), f"m rows {r0}.. not symmetric"
+        below = ar[None, :] <= ar[rows, None]
+        assert np.all(s[rows][below] == -1), f"s rows {r0}.."
