@@ -1134,9 +1134,17 @@ void plan_lockstep(TiledPlan &plan, const std::vector<int> &ids)
         std::vector<BulkLayout> &v = cache[(int64_t)NT * 64 + kb];
         if (v.empty()) {
             v.resize((size_t)NT + 1);
-            for (int E = 0; E <= NT; ++E)
-                v[E] = bulk_layout(NT, E, kb, plan.lone, plan.cus, plan.slots_per_cu,
-                                   plan.serial);
+            for (int E = 0; E <= NT; ++E) {
+                if (plan.chunk_target > 0) {
+                    const int tiles = NT - E > 1 ? NT - E : 1;
+                    int nch = plan.chunk_target / tiles;
+                    nch = nch < 1 ? 1 : (nch > kMaxChunks ? kMaxChunks : nch);
+                    v[E] = bulk_layout_chunks(NT, E, kb, nch);
+                } else {
+                    v[E] = bulk_layout(NT, E, kb, plan.lone, plan.cus, plan.slots_per_cu,
+                                       plan.serial);
+                }
+            }
         }
         return v;
     };
@@ -1319,7 +1327,7 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
 // The serial schedule: the plan's launch order already respects every
 // dependency (each launch follows everything it waits for), so one stream
 // runs it as is.
-static void plan_make_serial(TiledPlan &plan)
+void plan_make_serial(TiledPlan &plan)
 {
     for (TiledLaunch &L : plan.launches) {
         L.stream = 0;

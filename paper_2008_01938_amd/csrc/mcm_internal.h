@@ -261,6 +261,8 @@ struct TiledPlan {
     size_t part_elems = 0;             // partial-minima buffer (uint64) the plan needs
     bool lone = false;                 // one chain: fit bulk chunks to the GPU's slots
     bool serial = false;               // lone: one stream, chunks fitted to the whole device
+    int chunk_target = 0;              // > 0: about this many interior chunks per
+                                       // tile-diagonal (bulk_layout_chunks), device-independent
     int cus = 0;                       // lone: compute units of the device
     int slots_per_cu = 0;              // lone: resident k_bulk workgroups per CU
     int pair_min_blocks = 0;           // closures with more workgroups use the paired
@@ -284,6 +286,9 @@ struct ChainStep {
 };
 
 int32_t tiled_nt(int32_t n);
+// Every launch of a lone plan on the caller's stream, in plan order (which
+// already follows every dependency).
+void plan_make_serial(TiledPlan &plan);
 // lone: cus / slots_per_cu describe the device (TiledPlan); else ignored.
 // serial: the launches run alone on the device (every CU free).
 BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus = 0,
