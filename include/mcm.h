@@ -171,17 +171,49 @@ mcm_status mcm_solve_batched(int32_t count, const int32_t *n, const int64_t *p_o
  *                     MCM_ERR_INVALID_ARG before anything is enqueued.  The
  *                     plan is read only: solves of one plan may run on
  *                     several streams at once with distinct outputs.
- *   mcm_plan_autotune times the plan's closure shape (paired closures, two
- *                     per compute unit, for launches above a tile-count
- *                     threshold) at four thresholds on the given inputs and
- *                     keeps the fastest; writes m_all / s_all as a solve
- *                     does and synchronises `stream`.  *choice (may be NULL)
- *                     receives the threshold.  Must not run concurrently
- *                     with solves of the same plan.
+ *   mcm_plan_autotune times every configuration the plan can run on the
+ *                     given inputs and keeps the fastest for later solves.
+ *                     Configurations: 64-edge tiles with paired closures
+ *                     (two per compute unit) for launches above each of four
+ *                     tile-count thresholds, and, when every tiled chain has
+ *                     n <= 1024, 32-edge tiles (half the closure splits per
+ *                     cell, 63 closure steps per tile).  Each runs once
+ *                     untimed, then three times timed with events on
+ *                     `stream`; its fastest run counts.  The choice is also
+ *                     stored in a per-process tuning cache under the plan's
+ *                     bucket (device architecture, ceil(log2) of its largest
+ *                     tiled chain and of its tiled-chain count): plans
+ *                     created later for the same bucket, and
+ *                     mcm_solve_batched calls whose batch falls in it, start
+ *                     from it.  Writes m_all / s_all as a solve does and
+ *                     synchronises `stream`.  *choice (may be NULL) receives
+ *                     the index of the chosen configuration in
+ *                     mcm_plan_candidates' list (-1 if the plan has none).
+ *                     Must not run concurrently with solves of the same plan.
+ *   mcm_plan_config   the configuration solves use: tile edge (64 or 32),
+ *                     the paired-closure threshold in tiles, and its source
+ *                     (MCM_PLAN_DEFAULT: 64-edge tiles, threshold = the CU
+ *                     count; MCM_PLAN_CACHED: the tuning cache;
+ *                     MCM_PLAN_TUNED: this plan's autotune).  Any output
+ *                     pointer may be NULL.
+ *   mcm_plan_set_config  pins the configuration later solves use (tile
+ *                     edge 64 or 32, threshold >= 0, 0 meaning the CU
+ *                     count), e.g. one tuned elsewhere; MCM_ERR_UNSUPPORTED
+ *                     if the plan has no schedule for that edge (32 needs
+ *                     every tiled chain n <= 1024), MCM_ERR_INVALID_ARG for
+ *                     another edge or a negative threshold.  Its source
+ *                     becomes MCM_PLAN_TUNED, and the tuning cache keeps
+ *                     it for the plan's bucket as an autotune would.  Must
+ *                     not run concurrently with solves of the same plan.
+ *   mcm_plan_candidates  the configurations the plan can run, in autotune
+ *                     order: up to `cap` entries of tile edge, threshold (0:
+ *                     the CU count) and the last autotune's time in ms (-1
+ *                     if never timed); *count receives the full number.
  *   mcm_plan_destroy  frees the plan (its device tables with hipFree, so
  *                     after the device has finished with them); NULL is
  *                     ignored.
  */
+enum { MCM_PLAN_DEFAULT = 0, MCM_PLAN_CACHED = 1, MCM_PLAN_TUNED = 2 };
 typedef struct mcm_plan mcm_plan;
 mcm_status mcm_plan_create(int32_t count, const int32_t *n, const int64_t *p_off,
                            const int64_t *tab_off, int32_t max_dim, mcm_plan **out);
@@ -189,6 +221,11 @@ mcm_status mcm_plan_solve(const mcm_plan *plan, const int32_t *p_all, int64_t *m
                           int32_t *s_all, hipStream_t stream);
 mcm_status mcm_plan_autotune(mcm_plan *plan, const int32_t *p_all, int64_t *m_all,
                              int32_t *s_all, hipStream_t stream, int32_t *choice);
+mcm_status mcm_plan_config(const mcm_plan *plan, int32_t *tile_edge, int32_t *pair_min_blocks,
+                           int32_t *source);
+mcm_status mcm_plan_set_config(mcm_plan *plan, int32_t tile_edge, int32_t pair_min_blocks);
+mcm_status mcm_plan_candidates(const mcm_plan *plan, int32_t cap, int32_t *tile_edge,
+                               int32_t *pair_min_blocks, float *ms, int32_t *count);
 void mcm_plan_destroy(mcm_plan *plan);
 
 /*

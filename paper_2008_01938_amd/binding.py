@@ -31,12 +31,14 @@ ALGOS = {"auto": ALGO_AUTO, "wavefront": ALGO_WAVEFRONT, "tiled": ALGO_TILED,
 # Profiler kernel classes (mcm_profile_read).
 PROF_SETUP, PROF_BULK, PROF_CLOSE, PROF_WAVE, PROF_BATCH = range(5)
 PROFILE_SERIAL = 1 << 16   # MCM_PROFILE_SERIAL
+PLAN_SOURCES = {0: "default", 1: "cache", 2: "tuned"}   # MCM_PLAN_*
 
 # Every symbol include/mcm.h declares.
 EXPORTED = (
     "mcm_status_string", "mcm_version", "mcm_check_chain", "mcm_select_algo",
     "mcm_solve", "mcm_solve_algo", "mcm_solve_batched", "mcm_plan_create", "mcm_plan_solve",
-    "mcm_plan_autotune", "mcm_plan_destroy", "mcm_chain_create", "mcm_chain_solve", "mcm_chain_n",
+    "mcm_plan_autotune", "mcm_plan_config", "mcm_plan_set_config", "mcm_plan_candidates",
+    "mcm_plan_destroy", "mcm_chain_create", "mcm_chain_solve", "mcm_chain_n",
     "mcm_chain_destroy", "mcm_server_create", "mcm_server_submit", "mcm_server_poll",
     "mcm_server_release", "mcm_server_request_bytes", "mcm_server_stats", "mcm_server_destroy", "mcm_clock_now",
     "mcm_profile_enable", "mcm_profile_enable_mask", "mcm_profile_read", "mcm_parens_length", "mcm_parenthesize",
@@ -113,6 +115,16 @@ def load() -> ctypes.CDLL:
             lib.mcm_plan_solve.restype = ctypes.c_int
             lib.mcm_plan_autotune.argtypes = [vp, i32p, vp, vp, vp, ctypes.POINTER(ctypes.c_int32)]
             lib.mcm_plan_autotune.restype = ctypes.c_int
+            lib.mcm_plan_config.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 3
+            lib.mcm_plan_config.restype = ctypes.c_int
+            lib.mcm_plan_set_config.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+            lib.mcm_plan_set_config.restype = ctypes.c_int
+            lib.mcm_plan_candidates.argtypes = [vp, ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_int32),
+                                                ctypes.POINTER(ctypes.c_int32),
+                                                ctypes.POINTER(ctypes.c_float),
+                                                ctypes.POINTER(ctypes.c_int32)]
+            lib.mcm_plan_candidates.restype = ctypes.c_int
             lib.mcm_plan_destroy.argtypes = [vp]
             lib.mcm_plan_destroy.restype = None
             lib.mcm_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, vp,
@@ -503,7 +515,8 @@ class Plan:
             raise MCMError(st, "mcm_plan_solve")
 
     def autotune(self, p_all, m_all, s_all, stream=None) -> int:
-        """Time the closure-shape thresholds; returns the one kept."""
+        """Time every configuration (tile edge, closure threshold) on these
+        inputs and keep the fastest; returns its index in candidates()."""
         p_all = self._args(p_all, m_all, s_all)
         choice = ctypes.c_int32(0)
         st = load().mcm_plan_autotune(self._h, _p_ptr(p_all), ctypes.c_void_p(m_all.data_ptr()),
@@ -513,6 +526,38 @@ class Plan:
         if st != OK:
             raise MCMError(st, "mcm_plan_autotune")
         return int(choice.value)
+
+    def config(self) -> dict:
+        """{'tile_edge', 'pair_min_blocks', 'source'} of the configuration in use."""
+        v = [ctypes.c_int32(0) for _ in range(3)]
+        st = load().mcm_plan_config(self._h, *[ctypes.byref(x) for x in v])
+        if st != OK:
+            raise MCMError(st, "mcm_plan_config")
+        return {"tile_edge": v[0].value, "pair_min_blocks": v[1].value,
+                "source": PLAN_SOURCES[v[2].value]}
+
+    def set_config(self, tile_edge: int, pair_min_blocks: int = 0) -> None:
+        st = load().mcm_plan_set_config(self._h, int(tile_edge), int(pair_min_blocks))
+        if st != OK:
+            raise MCMError(st, "mcm_plan_set_config")
+
+    def candidates(self) -> list:
+        """[{'tile_edge', 'pair_min_blocks', 'ms'}] in autotune order (ms from
+        the last autotune, None if never timed)."""
+        cnt = ctypes.c_int32(0)
+        lib = load()
+        st = lib.mcm_plan_candidates(self._h, 0, None, None, None, ctypes.byref(cnt))
+        if st != OK:
+            raise MCMError(st, "mcm_plan_candidates")
+        k = cnt.value
+        te = (ctypes.c_int32 * max(k, 1))()
+        pm = (ctypes.c_int32 * max(k, 1))()
+        ms = (ctypes.c_float * max(k, 1))()
+        st = lib.mcm_plan_candidates(self._h, k, te, pm, ms, ctypes.byref(cnt))
+        if st != OK:
+            raise MCMError(st, "mcm_plan_candidates")
+        return [{"tile_edge": te[i], "pair_min_blocks": pm[i],
+                 "ms": None if ms[i] < 0 else float(ms[i])} for i in range(k)]
 
     def close(self) -> None:
         if self._h:

@@ -53,9 +53,10 @@
 namespace mcm {
 namespace {
 
-constexpr int T = 64;          // tile edge
+// Tile edges: 64 for lone chains and large batches, 32 for batches of small
+// chains (half the closure splits per cell, 63 closure steps per tile).
 constexpr int KC = 16;         // k values staged per LDS round (bulk)
-constexpr int NTH = 256;       // k_tri, k_tri_key and k_bulk threads
+constexpr int NTH = 256;       // k_tri and k_tri_key threads
 constexpr double kPad = 4611686018427387904.0;  // 2^62: never wins a min
 
 // The segment of a launch that workgroup b belongs to (segments are sorted
@@ -85,7 +86,7 @@ __device__ __forceinline__ int find_seg(const TileSeg *__restrict__ seg, int nse
 // OB: the optimal-BST weights (one chain; p_all then holds zeros): the
 // diagonal holds the gap weights q and every cell gains W(i, j) = hi[j] -
 // lo[i] after its minimum.
-template <bool OB>
+template <int T, bool OB>
 __global__ __launch_bounds__(NTH) void k_tri(const TileChain *__restrict__ chains,
                                              const TileSeg *__restrict__ segs, int nseg,
                                              const int32_t *__restrict__ p_all,
@@ -160,8 +161,9 @@ __global__ __launch_bounds__(NTH) void k_tri(const TileChain *__restrict__ chain
 // kernels (no weights): a split kl of cell (r, c) is the integer
 //   (m[r][kl] + m[kl+1][c] + p[r] p[kl+1] p[c+1]) * 2^kb + kl  <  2^53,
 // since every candidate cost is below 2^cost_bits and kb <= 53 - cost_bits
-// (and kl < 64 <= 2^kb), so every fma, add and min on it is exact and one
+// (and kl < T <= 2^kb), so every fma, add and min on it is exact and one
 // fmin picks the smallest cost, then the smallest kl.
+template <int T>
 __global__ __launch_bounds__(NTH) void k_tri_key(const TileChain *__restrict__ chains,
                                                  const TileSeg *__restrict__ segs, int nseg,
                                                  const double *__restrict__ pd_all,
@@ -220,12 +222,16 @@ __global__ __launch_bounds__(NTH) void k_tri_key(const TileChain *__restrict__ c
 // ------------------------------------------------------------------------
 // Shared memory and launch shapes.
 // ------------------------------------------------------------------------
-constexpr int CSTR = T + 8;          // closure: column stride (doubles) of its LDS tables
+// Closure: column stride (doubles) of its LDS tables; T + 8 is 8 (mod 16)
+// for both tile edges.
+template <int T>
+constexpr int cstr() { return T + 8; }
 
-// Closure shapes: G lanes per row group, T rows.  G = 16: one tile per CU
-// (16 waves, column-major DJ table).  G = 8: a tile in 8 waves with a packed
-// DJ table, small enough that two closure workgroups share a CU.
-template <int G>
+// Closure shapes: G lanes per row group, T rows.  (T, G) = (64, 16): one
+// tile per CU (16 waves, column-major DJ table).  (64, 8): a tile in 8 waves
+// with a packed DJ table, small enough that two closure workgroups share a
+// CU.  (32, 8): a 32-edge tile in 4 waves with the packed table.
+template <int T, int G>
 struct CloseShape {
     static constexpr int CG = G;          // lanes per row group
     static constexpr int CTH = T * G;     // threads
@@ -252,8 +258,10 @@ constexpr int dj_packed_base(int c)
 static_assert(dj_packed_base(1) == 8 && dj_packed_base(9) == 72 && dj_packed_base(16) == 240 &&
                   dj_packed_base(63) == 2424,
               "packed DJ bases");
-constexpr int kDJPacked = dj_packed_base(T - 1) + T;
+template <int T>
+constexpr int dj_packed_size() { return dj_packed_base(T - 1) + T; }
 
+template <int T>
 struct BulkLds {
     double As[2][KC][T + 1];  // As[kk][r] = m[row0+r][k] * 2^kb
     double Bs[2][KC][T];      // Bs[kk][c] = m[k+1][col0+c] * 2^kb + (k - k0)
@@ -265,11 +273,13 @@ struct BulkLds {
 // conflict-free when the 16 lanes served together touch distinct 8-byte
 // words modulo 16: with G = 16 those are one row group reading consecutive
 // rows of one column; with G = 8 two row groups reading adjacent columns,
-// whose starts differ by CSTR = 72 = 8 (mod 16) doubles.  Row T is a spare
-// so slot addresses never need clamping.
+// whose starts differ by CSTR = 8 (mod 16) doubles.  Row T is a spare so
+// slot addresses never need clamping.
 // The sweep reads column cc of the DJ table through its base offset, which a
 // lane advances as its cc grows by one (dj_next), so no per-step multiply.
+template <int T>
 struct CloseLdsFull {
+    static constexpr int CSTR = cstr<T>();
     double DJt[T][CSTR];   // DJt[c][q] = DJ[q][c] * 2^kb + T + q - 1 (1 <= q <= c), else 0
     double Xt[T][CSTR];    // Xt[c][q]: bulk key, then final cost * 2^kb of cell (q, c)
     int32_t Ks[T][T + 1];  // bulk split, then final split
@@ -281,8 +291,10 @@ struct CloseLdsFull {
     __device__ static int dj_next(int base, int) { return base + CSTR; }
     __device__ double dj_at_base(int base, int j) const { return (&DJt[0][0])[base + j + 1]; }
 };
+template <int T>
 struct CloseLdsPacked {
-    double DJp[kDJPacked];  // column c from dj_packed_base(c): DJ[q][c] at q - 1
+    static constexpr int CSTR = cstr<T>();
+    double DJp[dj_packed_size<T>()];  // column c from dj_packed_base(c): DJ[q][c] at q - 1
     double Xt[T][CSTR];
     int32_t Ks[T][T + 1];
     double pJs[T + 1];
@@ -295,16 +307,29 @@ struct CloseLdsPacked {
 
 // ------------------------------------------------------------------------
 // Bulk: workgroup b of a segment takes tile b / nch and chunk b % nch of
-// the segment's split range; thread (tx, ty) owns the cells rows ty + 16a,
-// columns tx + 16b (a, b = 0..3) of the tile.
+// the segment's split range; thread (tx, ty) owns the cells rows ty + TW*a,
+// columns tx + TW*b (a, b = 0..3, TW = T/4) of the tile: a 4 x 4 register
+// microtile, (T/4)^2 threads (256 for T = 64, one wave for T = 32).
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(NTH) void k_bulk(const TileChain *__restrict__ chains,
-                                              const TileSeg *__restrict__ segs, int nseg,
-                                              const int64_t *__restrict__ m_all,
-                                              const double *__restrict__ pd_all,
-                                              uint64_t *__restrict__ part_all)
+template <int T>
+constexpr int bulk_threads() { return (T / 4) * (T / 4); }
+
+template <int T>
+__global__ __launch_bounds__(bulk_threads<T>()) void k_bulk(const TileChain *__restrict__ chains,
+                                                            const TileSeg *__restrict__ segs,
+                                                            int nseg,
+                                                            const int64_t *__restrict__ m_all,
+                                                            const double *__restrict__ pd_all,
+                                                            uint64_t *__restrict__ part_all)
 {
-    __shared__ BulkLds L;
+    constexpr int BTH = bulk_threads<T>();
+    constexpr int TW = T / 4;            // threads per microtile row
+    constexpr int RA = BTH / KC;         // A rows staged apart per thread
+    constexpr int RB = BTH / T;          // B splits staged apart per thread
+    constexpr int V = T * KC / BTH;      // elements of each block per thread
+    static_assert(BTH % KC == 0 && BTH % T == 0 && RA * V == T && RB * V == KC && BTH >= KC,
+                  "staging map");
+    __shared__ BulkLds<T> L;
     const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
     const TileChain ch = chains[sg.chain];
     const int local = blockIdx.x - sg.first;
@@ -323,53 +348,52 @@ __global__ __launch_bounds__(NTH) void k_bulk(const TileChain *__restrict__ chai
     const int nJ = min(T, n - col0);
     const double scale = ldexp(1.0, kb);
     const double inv_scale = ldexp(1.0, -kb);
-    const int tx = tid & 15, ty = tid >> 4;
+    const int tx = tid % TW, ty = tid / TW;
 
     double pj[4][4], best[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        const double pi = pd[row0 + ty + 16 * a] * scale;
+        const double pi = pd[row0 + ty + TW * a] * scale;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int c = tx + 16 * b;
+            const int c = tx + TW * b;
             pj[a][b] = c < nJ ? pi * pd[col0 + c + 1] : 0.0;
             best[a][b] = __builtin_inf();
         }
     }
 
     // Staging: the A block is T rows x KC columns, the B block KC rows x T
-    // columns.  Thread tid stages A rows ar + 16v at split akk and B splits
-    // bkk + 4v at column bc (v = 0..3).  Only the round's base moves, so on
-    // a table under 2 GiB the loads take 32-bit byte offsets from a uniform
+    // columns.  Thread tid stages A rows ar + RA*v at split akk and B splits
+    // bkk + RB*v at column bc (v < V).  Only the round's base moves, so on a
+    // table under 2 GiB the loads take 32-bit byte offsets from a uniform
     // base.  In a round that passes kend, splits at or past it are staged
     // from split kend-1 (inside the table) and masked.
-    static_assert(NTH == 256 && KC == 16 && T == 64, "staging map");
     const int akk = tid % KC, ar = tid / KC;
     const int bcol = tid % T, bc = min(bcol, nJ - 1), bkk = tid / T;
     const bool narrow = (size_t)n * (size_t)n * sizeof(int64_t) < ((size_t)1 << 31);
-    uint32_t oa[4], ob[4];
+    uint32_t oa[V], ob[V];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        oa[v] = (uint32_t)(((size_t)(row0 + ar + 16 * v) * n + akk) * sizeof(int64_t));
-        ob[v] = (uint32_t)(((size_t)(bkk + 4 * v + 1) * n + col0 + bc) * sizeof(int64_t));
+    for (int v = 0; v < V; ++v) {
+        oa[v] = (uint32_t)(((size_t)(row0 + ar + RA * v) * n + akk) * sizeof(int64_t));
+        ob[v] = (uint32_t)(((size_t)(bkk + RB * v + 1) * n + col0 + bc) * sizeof(int64_t));
     }
-    int64_t ra[4], rb[4];
+    int64_t ra[V], rb[V];
     double rp = 0.0;
     auto load = [&](int kc) {
         if (kc + KC <= kend && narrow) {
             const char *ba = (const char *)(m + kc);
             const char *bb = (const char *)(m + (size_t)kc * n);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
+            for (int v = 0; v < V; ++v) {
                 ra[v] = *(const int64_t *)(ba + oa[v]);
                 rb[v] = *(const int64_t *)(bb + ob[v]);
             }
         } else {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
+            for (int v = 0; v < V; ++v) {
                 const int ka = min(kc + akk, kend - 1);
-                ra[v] = m[(size_t)(row0 + ar + 16 * v) * n + ka];
-                const int kb2 = min(kc + bkk + 4 * v, kend - 1);
+                ra[v] = m[(size_t)(row0 + ar + RA * v) * n + ka];
+                const int kb2 = min(kc + bkk + RB * v, kend - 1);
                 rb[v] = m[(size_t)(kb2 + 1) * n + col0 + bc];
             }
         }
@@ -378,11 +402,11 @@ __global__ __launch_bounds__(NTH) void k_bulk(const TileChain *__restrict__ chai
     auto store = [&](int kc, int buf) {
         const bool full = kc + KC <= kend;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            L.As[buf][akk][ar + 16 * v] =
+        for (int v = 0; v < V; ++v) {
+            L.As[buf][akk][ar + RA * v] =
                 (full || kc + akk < kend) ? (double)ra[v] * scale : kPad;
-            L.Bs[buf][bkk + 4 * v][bcol] =
-                fma((double)rb[v], scale, (double)(kc + bkk + 4 * v - k0));
+            L.Bs[buf][bkk + RB * v][bcol] =
+                fma((double)rb[v], scale, (double)(kc + bkk + RB * v - k0));
         }
         if (tid < KC) L.Ps[buf][tid] = rp;
     };
@@ -399,9 +423,9 @@ __global__ __launch_bounds__(NTH) void k_bulk(const TileChain *__restrict__ chai
         for (int kk = 0; kk < KC; ++kk) {
             double av[4], bv[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = L.As[buf][kk][ty + 16 * a];
+            for (int a = 0; a < 4; ++a) av[a] = L.As[buf][kk][ty + TW * a];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) bv[b] = L.Bs[buf][kk][tx + 16 * b];
+            for (int b = 0; b < 4; ++b) bv[b] = L.Bs[buf][kk][tx + TW * b];
             const double pk = L.Ps[buf][kk];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
@@ -419,7 +443,7 @@ __global__ __launch_bounds__(NTH) void k_bulk(const TileChain *__restrict__ chai
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int r = ty + 16 * a, c = tx + 16 * b;
+            const int r = ty + TW * a, c = tx + TW * b;
             uint64_t packed = UINT64_MAX;
             if (c < nJ) {
                 const double key = best[a][b];
@@ -471,20 +495,20 @@ __device__ __forceinline__ double min_group(double v)
     return v;
 }
 
-template <int G>
+template <int T, int G>
 struct CloseRegs {
-    double DIr[CloseShape<G>::CS], PIr[CloseShape<G>::CS], PJr[CloseShape<G>::CS],
-        Xrow[CloseShape<G>::CS];
+    double DIr[CloseShape<T, G>::CS], PIr[CloseShape<T, G>::CS], PJr[CloseShape<T, G>::CS],
+        Xrow[CloseShape<T, G>::CS];
 };
 
 // One step of a row group: the minimum over its (a) and (b) splits of cell
 // (r, cc).  Every (b) slot is read: a slot whose cell is not final yet still
 // holds Xrow = 2^62, so whatever DJ value it meets, its term loses.
-template <int G, int T0, class Lds>  // T0: first (a) slot any row of this wave uses
-__device__ __forceinline__ double close_step(const CloseRegs<G> &R, const Lds &L, int xo, int djb,
-                                             int g, double pJc)
+template <int T, int G, int T0, class Lds>  // T0: first (a) slot any row of this wave uses
+__device__ __forceinline__ double close_step(const CloseRegs<T, G> &R, const Lds &L, int xo,
+                                             int djb, int g, double pJc)
 {
-    constexpr int CS = CloseShape<G>::CS;
+    constexpr int CS = CloseShape<T, G>::CS;
     double xa[CS], xb[CS];
     const double *__restrict__ xcol = &L.Xt[0][0] + xo;  // column cc of Xt
 #pragma unroll
@@ -506,20 +530,20 @@ __device__ __forceinline__ double close_step(const CloseRegs<G> &R, const Lds &L
 }
 
 // close_step with its first (a) slot t0 (wave-uniform) as a template argument.
-template <int G, int T0, class Lds>
-__device__ __forceinline__ double close_step_at(int t0, const CloseRegs<G> &R, const Lds &L,
+template <int T, int G, int T0, class Lds>
+__device__ __forceinline__ double close_step_at(int t0, const CloseRegs<T, G> &R, const Lds &L,
                                                 int xo, int djb, int g, double pJc)
 {
-    if constexpr (T0 + 1 < CloseShape<G>::CS) {
-        if (t0 > T0) return close_step_at<G, T0 + 1>(t0, R, L, xo, djb, g, pJc);
+    if constexpr (T0 + 1 < CloseShape<T, G>::CS) {
+        if (t0 > T0) return close_step_at<T, G, T0 + 1>(t0, R, L, xo, djb, g, pJc);
     }
-    return close_step<G, T0>(R, L, xo, djb, g, pJc);
+    return close_step<T, G, T0>(R, L, xo, djb, g, pJc);
 }
 
 // OB: the optimal-BST weights (pd_all then holds zeros, so every product
 // term vanishes): a cell gains W(i, j) = ob_hi[j] - ob_lo[i] once its
 // minimum is known.  pJs then carries ob_hi of the tile's columns.
-template <int G, class Lds, bool OB>
+template <int T, int G, class Lds, bool OB>
 __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__ chains,
                                            const TileSeg *__restrict__ segs, int nseg,
                                            int64_t *__restrict__ m_all,
@@ -529,8 +553,9 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
                                            const double *__restrict__ ob_hi,
                                            const double *__restrict__ ob_lo)
 {
-    constexpr int CTH = CloseShape<G>::CTH, CS = CloseShape<G>::CS;
-    constexpr int CROWS = CloseShape<G>::CROWS;
+    constexpr int CTH = CloseShape<T, G>::CTH, CS = CloseShape<T, G>::CS;
+    constexpr int CROWS = CloseShape<T, G>::CROWS;
+    constexpr int CSTR = Lds::CSTR;
     const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
     const TileChain ch = chains[sg.chain];
     const int local = blockIdx.x - sg.first;
@@ -549,7 +574,7 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
 
     const int r = tid / G, g = tid % G;
     const int h = __builtin_amdgcn_readfirstlane(tid / 64);  // rows CROWS*h ..
-    CloseRegs<G> R;
+    CloseRegs<T, G> R;
     const double pi_s = pd[row0 + r] * scale;
 #pragma unroll
     for (int t = 0; t < CS; ++t) {
@@ -571,12 +596,12 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
     {
         double *z = &L.Xt[0][0];
         for (int idx = tid; idx < T * CSTR; idx += CTH) z[idx] = 0.0;
-        if constexpr (std::is_same<Lds, CloseLdsFull>::value) {
+        if constexpr (!Lds::kPacked) {
             double *zd = &L.dj(0, 0);
             for (int idx = tid; idx < T * CSTR; idx += CTH) zd[idx] = 0.0;
         } else {
             double *zd = &L.dj(1, 0);
-            for (int idx = tid; idx < kDJPacked; idx += CTH) zd[idx] = 0.0;
+            for (int idx = tid; idx < dj_packed_size<T>(); idx += CTH) zd[idx] = 0.0;
         }
     }
     __syncthreads();
@@ -667,7 +692,7 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
             }
             const double pJc = L.pJs[cc + 1];
             const double xbulk = (&L.Xt[0][0])[xo + r];
-            const double best = close_step_at<G, 0>((h * CROWS) / G, R, L, xo, djb, g, pJc);
+            const double best = close_step_at<T, G, 0>((h * CROWS) / G, R, L, xo, djb, g, pJc);
             const double fin = fmin(best, xbulk);
             const double base = floor(fin * inv_scale);
             const double cost = OB ? base + (pJc - w_row) : base;
@@ -705,60 +730,63 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
 }
 
 // One tile per CU (lone chains: the closure is their critical path).
-__global__ __launch_bounds__(CloseShape<CG_LONE>::CTH) void k_close(
+__global__ __launch_bounds__((CloseShape<64, CG_LONE>::CTH)) void k_close(
     const TileChain *__restrict__ chains, const TileSeg *__restrict__ segs, int nseg,
     int64_t *__restrict__ m_all, int32_t *__restrict__ s_all, const double *__restrict__ pd_all,
     const uint64_t *__restrict__ part_all)
 {
-    __shared__ CloseLdsFull L;
-    close_tile<CG_LONE, CloseLdsFull, false>(L, chains, segs, nseg, m_all, s_all, pd_all,
-                                             part_all, nullptr, nullptr);
+    __shared__ CloseLdsFull<64> L;
+    close_tile<64, CG_LONE, CloseLdsFull<64>, false>(L, chains, segs, nseg, m_all, s_all, pd_all,
+                                                     part_all, nullptr, nullptr);
 }
 
-// Two tiles per CU (many chains: closure throughput matters).
-__global__ __launch_bounds__(CloseShape<CG_PAIR>::CTH) void k_close_pair(
+// Two tiles per CU (many chains: closure throughput matters); the same
+// shape serves the 32-edge tiles of batches of small chains, several per CU.
+template <int T>
+__global__ __launch_bounds__((CloseShape<T, CG_PAIR>::CTH)) void k_close_pair(
     const TileChain *__restrict__ chains, const TileSeg *__restrict__ segs, int nseg,
     int64_t *__restrict__ m_all, int32_t *__restrict__ s_all, const double *__restrict__ pd_all,
     const uint64_t *__restrict__ part_all)
 {
-    __shared__ CloseLdsPacked L;
-    close_tile<CG_PAIR, CloseLdsPacked, false>(L, chains, segs, nseg, m_all, s_all, pd_all,
-                                               part_all, nullptr, nullptr);
+    __shared__ CloseLdsPacked<T> L;
+    close_tile<T, CG_PAIR, CloseLdsPacked<T>, false>(L, chains, segs, nseg, m_all, s_all, pd_all,
+                                                     part_all, nullptr, nullptr);
 }
 
 // The same closures with the optimal-BST weights.
-__global__ __launch_bounds__(CloseShape<CG_LONE>::CTH) void k_close_ob(
+__global__ __launch_bounds__((CloseShape<64, CG_LONE>::CTH)) void k_close_ob(
     const TileChain *__restrict__ chains, const TileSeg *__restrict__ segs, int nseg,
     int64_t *__restrict__ m_all, int32_t *__restrict__ s_all, const double *__restrict__ pd_all,
     const uint64_t *__restrict__ part_all, const double *__restrict__ ob_hi,
     const double *__restrict__ ob_lo)
 {
-    __shared__ CloseLdsFull L;
-    close_tile<CG_LONE, CloseLdsFull, true>(L, chains, segs, nseg, m_all, s_all, pd_all,
-                                            part_all, ob_hi, ob_lo);
+    __shared__ CloseLdsFull<64> L;
+    close_tile<64, CG_LONE, CloseLdsFull<64>, true>(L, chains, segs, nseg, m_all, s_all, pd_all,
+                                                    part_all, ob_hi, ob_lo);
 }
 
 // Four waves per SIMD: without the bound the weight terms take it past the
 // 128 VGPRs that two workgroups per CU allow.
-__global__ __launch_bounds__(CloseShape<CG_PAIR>::CTH, 4) void k_close_pair_ob(
+__global__ __launch_bounds__((CloseShape<64, CG_PAIR>::CTH), 4) void k_close_pair_ob(
     const TileChain *__restrict__ chains, const TileSeg *__restrict__ segs, int nseg,
     int64_t *__restrict__ m_all, int32_t *__restrict__ s_all, const double *__restrict__ pd_all,
     const uint64_t *__restrict__ part_all, const double *__restrict__ ob_hi,
     const double *__restrict__ ob_lo)
 {
-    __shared__ CloseLdsPacked L;
-    close_tile<CG_PAIR, CloseLdsPacked, true>(L, chains, segs, nseg, m_all, s_all, pd_all,
-                                              part_all, ob_hi, ob_lo);
+    __shared__ CloseLdsPacked<64> L;
+    close_tile<64, CG_PAIR, CloseLdsPacked<64>, true>(L, chains, segs, nseg, m_all, s_all, pd_all,
+                                                      part_all, ob_hi, ob_lo);
 }
 
-static_assert(2 * sizeof(CloseLdsPacked) <= 163840, "two paired closures per CU");
+static_assert(2 * sizeof(CloseLdsPacked<64>) <= 163840, "two paired closures per CU");
 
 // Dynamic LDS requested on top of CloseLdsFull by every lone closure launch,
 // so that no bulk workgroup fits beside it on a CU (160 KB per CU): the
 // sweep is latency-bound and slows down several-fold next to a bulk
 // workgroup.
-constexpr size_t kCloseExtraLds = 163840 - sizeof(CloseLdsFull) - sizeof(BulkLds) + 1024;
-static_assert(sizeof(CloseLdsFull) + kCloseExtraLds <= 163840, "closure LDS exceeds a CU");
+constexpr size_t kCloseExtraLds =
+    163840 - sizeof(CloseLdsFull<64>) - sizeof(BulkLds<64>) + 1024;
+static_assert(sizeof(CloseLdsFull<64>) + kCloseExtraLds <= 163840, "closure LDS exceeds a CU");
 
 // A bounded pause (constant-rate wall clock) on the stream it runs on.
 __global__ __launch_bounds__(64) void k_delay(long long ticks)
@@ -801,7 +829,7 @@ int32_t bitlen_u64(uint64_t v)
     return b;
 }
 
-double tri_evals(int32_t n, int32_t NT)
+double tri_evals(int32_t n, int32_t NT, int32_t T)
 {
     double ev = 0.0;
     for (int32_t I = 0; I < NT; ++I) {
@@ -813,7 +841,7 @@ double tri_evals(int32_t n, int32_t NT)
 
 // Valid cells of the NT - D tiles of tile-diagonal D (the last tile column
 // may be ragged).
-double diag_cells(int32_t n, int32_t NT, int32_t D)
+double diag_cells(int32_t n, int32_t NT, int32_t D, int32_t T)
 {
     const int32_t nlast = n - (NT - 1) * T;
     return (double)(NT - D - 1) * T * T + (double)T * nlast;
@@ -838,8 +866,8 @@ double wave_cost(int64_t units, int32_t ks, int64_t slots)
 
 }  // namespace
 
-BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus, int slots_per_cu,
-                       bool serial)
+BulkLayout bulk_layout(int32_t T, int32_t NT, int32_t E, int32_t kb, bool lone, int cus,
+                       int slots_per_cu, bool serial)
 {
     BulkLayout bl{};
     if (E < 2 || E >= NT) return bl;
@@ -932,9 +960,9 @@ BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus, in
     return bl;
 }
 
-BulkLayout bulk_layout_chunks(int32_t NT, int32_t E, int32_t kb, int32_t nch)
+BulkLayout bulk_layout_chunks(int32_t T, int32_t NT, int32_t E, int32_t kb, int32_t nch)
 {
-    BulkLayout bl = bulk_layout(NT, E, kb, false);
+    BulkLayout bl = bulk_layout(T, NT, E, kb, false);
     if (E < 3 || E >= NT) return bl;
     const int32_t L = (E - 3) * T + 1;
     int32_t cap = kb >= 30 ? (1 << 30) : (1 << kb);
@@ -954,11 +982,11 @@ BulkLayout bulk_layout_chunks(int32_t NT, int32_t E, int32_t kb, int32_t nch)
     return bl;
 }
 
-size_t bulk_part_max(int32_t NT, int32_t kb)
+size_t bulk_part_max(int32_t T, int32_t NT, int32_t kb)
 {
     size_t most = 0;
     for (int32_t E = 2; E < NT; ++E) {
-        const size_t e = bulk_layout_chunks(NT, E, kb, kMaxChunks).elems;
+        const size_t e = bulk_layout_chunks(T, NT, E, kb, kMaxChunks).elems;
         if (e > most) most = e;
     }
     return most;
@@ -972,7 +1000,8 @@ int bulk_blocks_per_cu()
     static std::unordered_map<int, int> cache;
     std::lock_guard<std::mutex> lk(mu);
     int &nb = cache[device];
-    if (nb == 0 && hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bulk, NTH, 0) !=
+    if (nb == 0 && hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bulk<64>,
+                                                                 bulk_threads<64>(), 0) !=
                        hipSuccess)
         nb = 0;
     return nb;
@@ -984,7 +1013,7 @@ bool tiled_accepts(const ChainInfo &ci)
     return ci.cost_bits + 7 <= 53 && ci.cost_bits + kbits <= 64;
 }
 
-int32_t tiled_nt(int32_t n) { return (n + T - 1) / T; }
+int32_t tiled_nt(int32_t n, int32_t T) { return (n + T - 1) / T; }
 
 int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t s_off,
                    int64_t p_off, int64_t pd_off)
@@ -999,12 +1028,13 @@ int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t 
     if (c.kb > 20) c.kb = 20;
     c.kbits = bitlen_u64((uint64_t)(ci.n > 1 ? ci.n - 1 : 1));
     plan.chains.push_back(c);
-    plan.NT.push_back(tiled_nt(ci.n));
+    plan.NT.push_back(tiled_nt(ci.n, plan.T));
     return (int)plan.chains.size() - 1;
 }
 
 void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
 {
+    const int32_t T = plan.T;
     auto push = [&](TiledLaunch L, int wait) {
         L.wait = wait;
         if (wait >= 0) plan.launches[wait].record = true;
@@ -1024,7 +1054,7 @@ void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
         plan.segs.push_back(sg);
         tri.nseg += 1;
         tri.blocks += plan.NT[cs.chain];
-        tri.evals += tri_evals(plan.chains[cs.chain].n, plan.NT[cs.chain]);
+        tri.evals += tri_evals(plan.chains[cs.chain].n, plan.NT[cs.chain], T);
     }
     if (tri.nseg) push(tri, -1);
 
@@ -1053,7 +1083,7 @@ void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
         const double per_last =
             (double)nlast * T * (T - 1) / 2.0 + (double)T * nlast * (nlast - 1) / 2.0;
         close.evals += (double)(NT - D - 1) * per_full + per_last;
-        if (D == 1) close.evals += diag_cells(n, NT, D);
+        if (D == 1) close.evals += diag_cells(n, NT, D, T);
     }
     // The interior bulk of D+1 needs the closure of D-1, complete once the
     // launches before this closure on the caller's stream are.
@@ -1079,7 +1109,7 @@ void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
         plan.segs.push_back(sg);
         Lc.nseg += 1;
         Lc.blocks += (NT - E) * nch;
-        Lc.evals += diag_cells(plan.chains[c].n, NT, E) * klen;
+        Lc.evals += diag_cells(plan.chains[c].n, NT, E, T) * klen;
     };
     // Interior bulk of D+1 (aux stream): needs tile-diagonals <= D-1 only,
     // so it waits for the previous closure, not this one.
@@ -1139,10 +1169,10 @@ void plan_lockstep(TiledPlan &plan, const std::vector<int> &ids)
                     const int tiles = NT - E > 1 ? NT - E : 1;
                     int nch = plan.chunk_target / tiles;
                     nch = nch < 1 ? 1 : (nch > kMaxChunks ? kMaxChunks : nch);
-                    v[E] = bulk_layout_chunks(NT, E, kb, nch);
+                    v[E] = bulk_layout_chunks(plan.T, NT, E, kb, nch);
                 } else {
-                    v[E] = bulk_layout(NT, E, kb, plan.lone, plan.cus, plan.slots_per_cu,
-                                       plan.serial);
+                    v[E] = bulk_layout(plan.T, NT, E, kb, plan.lone, plan.cus,
+                                       plan.slots_per_cu, plan.serial);
                 }
             }
         }
@@ -1221,7 +1251,8 @@ mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double 
 
 mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const TileSeg *segs,
                            const int32_t *p, const double *pd, int64_t *m_all, int32_t *s_all,
-                           uint64_t *part_ext, hipStream_t stream, const ObstWeights *ob)
+                           uint64_t *part_ext, hipStream_t stream, const ObstWeights *ob,
+                           int pair_min_blocks)
 {
     if (plan.launches.empty()) return MCM_OK;
     mcm_status st = MCM_OK;
@@ -1270,38 +1301,51 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
         if (L.kind == TK_TRI) {
             ProfileScope ps(KC_SETUP, q, L.evals);
             if (ob)
-                hipLaunchKernelGGL(k_tri<true>, dim3(L.blocks), dim3(NTH), 0, q, chains, sg,
+                hipLaunchKernelGGL((k_tri<64, true>), dim3(L.blocks), dim3(NTH), 0, q, chains, sg,
                                    L.nseg, p, m_all, s_all, ob->hi, ob->lo, ob->q);
+            else if (plan.T == 32)
+                hipLaunchKernelGGL(k_tri_key<32>, dim3(L.blocks), dim3(NTH), 0, q, chains, sg,
+                                   L.nseg, pd, m_all, s_all);
             else
-                hipLaunchKernelGGL(k_tri_key, dim3(L.blocks), dim3(NTH), 0, q, chains, sg, L.nseg,
-                                   pd, m_all, s_all);
+                hipLaunchKernelGGL(k_tri_key<64>, dim3(L.blocks), dim3(NTH), 0, q, chains, sg,
+                                   L.nseg, pd, m_all, s_all);
             e = hipGetLastError();
         } else if (L.kind == TK_BULK) {
             ProfileScope ps(KC_BULK, q, L.evals);
-            hipLaunchKernelGGL(k_bulk, dim3(L.blocks), dim3(NTH), 0, q, chains, sg, L.nseg,
-                               m_all, pd, part);
+            if (plan.T == 32)
+                hipLaunchKernelGGL(k_bulk<32>, dim3(L.blocks), dim3(bulk_threads<32>()), 0, q,
+                                   chains, sg, L.nseg, m_all, pd, part);
+            else
+                hipLaunchKernelGGL(k_bulk<64>, dim3(L.blocks), dim3(bulk_threads<64>()), 0, q,
+                                   chains, sg, L.nseg, m_all, pd, part);
             e = hipGetLastError();
         } else if (L.kind == TK_CLOSE) {
             ProfileScope ps(KC_CLOSE, q, L.evals);
             // Paired closures (two per CU, each somewhat slower) only when
             // the launch has more tiles than the device has CUs (or than
             // the plan's tuned threshold).
-            const int pair_min = plan.pair_min_blocks > 0 ? plan.pair_min_blocks : cus;
+            const int tuned = pair_min_blocks >= 0 ? pair_min_blocks : plan.pair_min_blocks;
+            const int pair_min = tuned > 0 ? tuned : cus;
             const bool lone = plan.lone || L.blocks <= pair_min;
-            if (ob && lone)
-                hipLaunchKernelGGL(k_close_ob, dim3(L.blocks), dim3(CloseShape<CG_LONE>::CTH),
-                                   kCloseExtraLds, q, chains, sg, L.nseg, m_all, s_all, pd, part,
-                                   ob->hid, ob->lod);
+            if (plan.T == 32)
+                hipLaunchKernelGGL(k_close_pair<32>, dim3(L.blocks),
+                                   dim3(CloseShape<32, CG_PAIR>::CTH), 0, q, chains, sg, L.nseg,
+                                   m_all, s_all, pd, part);
+            else if (ob && lone)
+                hipLaunchKernelGGL(k_close_ob, dim3(L.blocks),
+                                   dim3(CloseShape<64, CG_LONE>::CTH), kCloseExtraLds, q, chains,
+                                   sg, L.nseg, m_all, s_all, pd, part, ob->hid, ob->lod);
             else if (ob)
                 hipLaunchKernelGGL(k_close_pair_ob, dim3(L.blocks),
-                                   dim3(CloseShape<CG_PAIR>::CTH), 0, q, chains, sg, L.nseg,
+                                   dim3(CloseShape<64, CG_PAIR>::CTH), 0, q, chains, sg, L.nseg,
                                    m_all, s_all, pd, part, ob->hid, ob->lod);
             else if (lone)
-                hipLaunchKernelGGL(k_close, dim3(L.blocks), dim3(CloseShape<CG_LONE>::CTH),
+                hipLaunchKernelGGL(k_close, dim3(L.blocks), dim3(CloseShape<64, CG_LONE>::CTH),
                                    kCloseExtraLds, q, chains, sg, L.nseg, m_all, s_all, pd, part);
             else
-                hipLaunchKernelGGL(k_close_pair, dim3(L.blocks), dim3(CloseShape<CG_PAIR>::CTH),
-                                   0, q, chains, sg, L.nseg, m_all, s_all, pd, part);
+                hipLaunchKernelGGL(k_close_pair<64>, dim3(L.blocks),
+                                   dim3(CloseShape<64, CG_PAIR>::CTH), 0, q, chains, sg, L.nseg,
+                                   m_all, s_all, pd, part);
             e = hipGetLastError();
         }
         if (e == hipSuccess && L.record && aux) {

@@ -5,9 +5,11 @@
 
 #include <algorithm>
 #include <atomic>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
+#include <string>
 #include <string.h>
 #include <unordered_map>
 #include <vector>
@@ -476,6 +478,64 @@ struct mcm_chain {
     void *block = nullptr;
 };
 
+// One tile edge's schedule of a batched plan, its tables in device memory.
+struct PlanVariant {
+    TiledPlan tp;
+    void *tables = nullptr;  // device: TileChain records, then TileSeg from seg_off
+    size_t seg_off = 0;
+};
+
+// A configuration a batched plan can run: tile edge and closure-shape
+// threshold (64-edge tiles: launches with more tiles use two per CU).
+struct PlanConfig {
+    int T = 64;
+    int pair_min = 0;  // 0: the device's CU count
+};
+
+namespace {
+
+// Largest tiled chain for which a plan also builds the 32-edge schedule.
+constexpr int32_t kSmallTileMaxN = 1024;
+
+// Tuning cache: the configuration the last autotune chose for a batch shape
+// bucket on a device architecture, used by later plans and one-shot batched
+// solves of the same bucket.
+std::mutex g_tune_mu;
+std::map<std::string, PlanConfig> g_tune;
+
+std::string device_arch(int device)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+    return prop.gcnArchName;
+}
+
+int32_t ceil_log2(int64_t v)
+{
+    int32_t b = 0;
+    while (((int64_t)1 << b) < v) ++b;
+    return b;
+}
+
+// Bucket of a batch: the architecture, ceil(log2) of its largest tiled
+// chain and of its number of tiled chains.
+std::string tune_key(int device, int32_t max_n, int64_t count)
+{
+    return device_arch(device) + "/n" + std::to_string(ceil_log2(max_n)) + "/c" +
+           std::to_string(ceil_log2(count));
+}
+
+bool tune_lookup(const std::string &key, PlanConfig *out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+}  // namespace
+
 struct mcm_plan {
     int32_t count = 0, max_dim = 0;
     int device = -1;
@@ -484,12 +544,17 @@ struct mcm_plan {
     std::vector<ChainInfo> ci;     // per chain, from n and max_dim
     std::vector<int32_t> wavefront;  // chains outside the tiled range
     int64_t p_len = 0;              // dims read: p_all[0 .. p_len)
-    TiledPlan tp;
-    void *tables = nullptr;         // device: TileChain records, then TileSeg from seg_off
-    size_t seg_off = 0;
+    PlanVariant var[2];             // [0]: 64-edge tiles; [1]: 32-edge tiles (small chains only)
+    bool has_var[2] = {false, false};
+    PlanConfig cfg;                 // the configuration solves use
+    int32_t source = MCM_PLAN_DEFAULT;
+    std::string key;                // tuning-cache bucket
+    std::vector<PlanConfig> cands;  // configurations the plan can run
+    std::vector<float> cand_ms;     // their times in the last autotune (-1: not timed)
     ~mcm_plan()
     {
-        if (tables) (void)hipFree(tables);
+        for (PlanVariant &v : var)
+            if (v.tables) (void)hipFree(v.tables);
     }
 };
 
@@ -557,16 +622,28 @@ mcm_status mcm_solve_batched(int32_t count, const int32_t *n, const int64_t *p_o
         return st;
     }
 
-    TiledPlan plan;
-    std::vector<int> ids;
-    int maxNT = 0;
+    // The configuration the tuning cache holds for this batch's bucket (see
+    // mcm_plan_autotune), else 64-edge tiles.
+    int32_t max_n = 1;
+    int64_t tiled_count = 0;
     for (int32_t b = 0; b < count; ++b) {
         if (!tiled_accepts(ci[b])) continue;
-        const int c = plan_add_chain(plan, ci[b], tab_off[b], tab_off[b], p_off[b], p_off[b]);
-        ids.push_back(c);
-        if (plan.NT[c] > maxNT) maxNT = plan.NT[c];
+        max_n = n[b] > max_n ? n[b] : max_n;
+        tiled_count += 1;
     }
-    (void)maxNT;
+    PlanConfig cfg;
+    int device = 0;
+    if (tiled_count > 0 && hipGetDevice(&device) == hipSuccess)
+        (void)tune_lookup(tune_key(device, max_n, tiled_count), &cfg);
+    if (max_n > kSmallTileMaxN) cfg.T = 64;
+    TiledPlan plan;
+    plan.T = cfg.T;
+    plan.pair_min_blocks = cfg.pair_min;
+    std::vector<int> ids;
+    for (int32_t b = 0; b < count; ++b) {
+        if (!tiled_accepts(ci[b])) continue;
+        ids.push_back(plan_add_chain(plan, ci[b], tab_off[b], tab_off[b], p_off[b], p_off[b]));
+    }
     plan_lockstep(plan, ids);
     st = run_tiled_plan(plan, p_dev, pd_dev, m_all, s_all, nullptr, stream);
     for (int32_t b = 0; b < count && st == MCM_OK; ++b) {
@@ -605,26 +682,52 @@ mcm_status mcm_plan_create(int32_t count, const int32_t *n, const int64_t *p_off
     if (!ranges_disjoint(count, n, tab_off, true)) return MCM_ERR_INVALID_ARG;
     if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
     if (hipGetDevice(&pl->device) != hipSuccess) return MCM_ERR_DEVICE;
-    std::vector<int> ids;
+    std::vector<int32_t> tiled;
+    int32_t max_n = 1;
     for (int32_t b = 0; b < count; ++b) {
         if (!tiled_accepts(pl->ci[b])) {
             pl->wavefront.push_back(b);
             continue;
         }
-        ids.push_back(plan_add_chain(pl->tp, pl->ci[b], tab_off[b], tab_off[b], p_off[b],
-                                     p_off[b]));
+        tiled.push_back(b);
+        max_n = n[b] > max_n ? n[b] : max_n;
     }
-    plan_lockstep(pl->tp, ids);
-    if (!pl->tp.launches.empty()) {
-        const size_t bytes = plan_tables_bytes(pl->tp, &pl->seg_off);
+    pl->has_var[0] = !tiled.empty();
+    pl->has_var[1] = !tiled.empty() && max_n <= kSmallTileMaxN;
+    for (int v = 0; v < 2; ++v) {
+        if (!pl->has_var[v]) continue;
+        PlanVariant &pv = pl->var[v];
+        pv.tp.T = v == 0 ? 64 : 32;
+        std::vector<int> ids;
+        for (int32_t b : tiled)
+            ids.push_back(plan_add_chain(pv.tp, pl->ci[b], tab_off[b], tab_off[b], p_off[b],
+                                         p_off[b]));
+        plan_lockstep(pv.tp, ids);
+        if (pv.tp.launches.empty()) continue;
+        const size_t bytes = plan_tables_bytes(pv.tp, &pv.seg_off);
         std::vector<char> host(bytes);
-        plan_tables_write(pl->tp, host.data());
-        if (hipMalloc(&pl->tables, bytes) != hipSuccess) {
-            pl->tables = nullptr;
+        plan_tables_write(pv.tp, host.data());
+        if (hipMalloc(&pv.tables, bytes) != hipSuccess) {
+            pv.tables = nullptr;
             return MCM_ERR_NO_MEMORY;
         }
-        if (hipMemcpy(pl->tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+        if (hipMemcpy(pv.tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
             return MCM_ERR_DEVICE;
+    }
+    // Candidates: 64-edge tiles at four closure-shape thresholds, then
+    // 32-edge tiles.
+    const int cus = device_cus();
+    if (pl->has_var[0])
+        for (int pm : {cus, cus / 2, 2 * cus, 4 * cus}) pl->cands.push_back(PlanConfig{64, pm});
+    if (pl->has_var[1]) pl->cands.push_back(PlanConfig{32, 0});
+    pl->cand_ms.assign(pl->cands.size(), -1.0f);
+    if (!tiled.empty()) {
+        pl->key = tune_key(pl->device, max_n, (int64_t)tiled.size());
+        PlanConfig c;
+        if (tune_lookup(pl->key, &c) && pl->has_var[c.T == 32 ? 1 : 0]) {
+            pl->cfg = c;
+            pl->source = MCM_PLAN_CACHED;
+        }
     }
     *out = pl.release();
     return MCM_OK;
@@ -635,7 +738,7 @@ mcm_status mcm_plan_create(int32_t count, const int32_t *n, const int64_t *p_off
 namespace {
 
 mcm_status plan_solve(const mcm_plan *pl, const int32_t *p_all, int64_t *m_all, int32_t *s_all,
-                      hipStream_t stream, int pair_min_blocks)
+                      hipStream_t stream, const PlanConfig &cfg)
 {
     if (pl == nullptr || p_all == nullptr) return MCM_ERR_INVALID_ARG;
     if (pl->count == 0) return MCM_OK;
@@ -669,18 +772,11 @@ mcm_status plan_solve(const mcm_plan *pl, const int32_t *p_all, int64_t *m_all, 
     }
     const int32_t *p_dev = (const int32_t *)dims;
     st = widen_dims(p_dev, pd, np, stream);
-    if (st == MCM_OK && pl->tables) {
-        TiledPlan tp_view;  // shares nothing mutable: a copy only when the threshold differs
-        const TiledPlan *tp = &pl->tp;
-        if (pair_min_blocks != pl->tp.pair_min_blocks) {
-            tp_view = pl->tp;
-            tp_view.pair_min_blocks = pair_min_blocks;
-            tp = &tp_view;
-        }
-        st = exec_tiled_plan(*tp, (const TileChain *)pl->tables,
-                             (const TileSeg *)((const char *)pl->tables + pl->seg_off), p_dev, pd,
-                             m_all, s_all, nullptr, stream);
-    }
+    const PlanVariant &pv = pl->var[cfg.T == 32 && pl->has_var[1] ? 1 : 0];
+    if (st == MCM_OK && pv.tables)
+        st = exec_tiled_plan(pv.tp, (const TileChain *)pv.tables,
+                             (const TileSeg *)((const char *)pv.tables + pv.seg_off), p_dev, pd,
+                             m_all, s_all, nullptr, stream, nullptr, cfg.pair_min);
     for (size_t u = 0; u < pl->wavefront.size() && st == MCM_OK; ++u) {
         const int32_t b = pl->wavefront[u];
         DeviceChain dc;
@@ -701,22 +797,20 @@ mcm_status mcm_plan_solve(const mcm_plan *plan, const int32_t *p_all, int64_t *m
                           int32_t *s_all, hipStream_t stream)
 {
     if (plan == nullptr) return MCM_ERR_INVALID_ARG;
-    return plan_solve(plan, p_all, m_all, s_all, stream, plan->tp.pair_min_blocks);
+    return plan_solve(plan, p_all, m_all, s_all, stream, plan->cfg);
 }
 
 mcm_status mcm_plan_autotune(mcm_plan *plan, const int32_t *p_all, int64_t *m_all,
                              int32_t *s_all, hipStream_t stream, int32_t *choice)
 {
     if (plan == nullptr) return MCM_ERR_INVALID_ARG;
-    if (plan->count == 0 || plan->tables == nullptr) {
-        if (choice) *choice = plan->tp.pair_min_blocks;
+    if (plan->count == 0 || plan->cands.empty()) {
+        if (choice) *choice = -1;
         return MCM_OK;
     }
-    // Candidate closure thresholds: paired closures for launches with more
-    // than this many tiles.  Each candidate is run twice; the second run is
-    // timed with events on the caller's stream.
-    const int cus = device_cus();
-    const int cand[] = {cus, cus / 2, 2 * cus, 4 * cus};
+    // Every candidate runs once untimed, then kTuneReps times, each timed
+    // with events on the caller's stream; the fastest run counts.
+    constexpr int kTuneReps = 3;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess) return MCM_ERR_DEVICE;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -724,28 +818,73 @@ mcm_status mcm_plan_autotune(mcm_plan *plan, const int32_t *p_all, int64_t *m_al
         return MCM_ERR_DEVICE;
     }
     mcm_status st = MCM_OK;
-    float best_ms = 0.f;
-    int best = cus;
-    for (int c = 0; c < (int)(sizeof(cand) / sizeof(cand[0])) && st == MCM_OK; ++c) {
-        st = plan_solve(plan, p_all, m_all, s_all, stream, cand[c]);
-        if (st != MCM_OK) break;
-        if (hipEventRecord(e0, stream) != hipSuccess) st = MCM_ERR_DEVICE;
-        if (st == MCM_OK) st = plan_solve(plan, p_all, m_all, s_all, stream, cand[c]);
-        if (st == MCM_OK && hipEventRecord(e1, stream) != hipSuccess) st = MCM_ERR_DEVICE;
-        float ms = 0.f;
-        if (st == MCM_OK && (hipEventSynchronize(e1) != hipSuccess ||
-                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-            st = MCM_ERR_DEVICE;
-        if (st == MCM_OK && (c == 0 || ms < best_ms)) {
-            best_ms = ms;
-            best = cand[c];
+    int best = 0;
+    for (size_t c = 0; c < plan->cands.size() && st == MCM_OK; ++c) {
+        st = plan_solve(plan, p_all, m_all, s_all, stream, plan->cands[c]);
+        float fastest = -1.0f;
+        for (int r = 0; r < kTuneReps && st == MCM_OK; ++r) {
+            if (hipEventRecord(e0, stream) != hipSuccess) st = MCM_ERR_DEVICE;
+            if (st == MCM_OK) st = plan_solve(plan, p_all, m_all, s_all, stream, plan->cands[c]);
+            if (st == MCM_OK && hipEventRecord(e1, stream) != hipSuccess) st = MCM_ERR_DEVICE;
+            float ms = 0.f;
+            if (st == MCM_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                st = MCM_ERR_DEVICE;
+            if (st == MCM_OK && (fastest < 0.f || ms < fastest)) fastest = ms;
         }
+        plan->cand_ms[c] = fastest;
+        if (st == MCM_OK && fastest < plan->cand_ms[(size_t)best]) best = (int)c;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != MCM_OK) return st;
-    plan->tp.pair_min_blocks = best;
+    plan->cfg = plan->cands[(size_t)best];
+    plan->source = MCM_PLAN_TUNED;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[plan->key] = plan->cfg;
+    }
     if (choice) *choice = best;
+    return MCM_OK;
+}
+
+mcm_status mcm_plan_config(const mcm_plan *plan, int32_t *tile_edge, int32_t *pair_min_blocks,
+                           int32_t *source)
+{
+    if (plan == nullptr) return MCM_ERR_INVALID_ARG;
+    if (tile_edge) *tile_edge = plan->cfg.T;
+    if (pair_min_blocks) *pair_min_blocks = plan->cfg.pair_min > 0 ? plan->cfg.pair_min
+                                                                   : device_cus();
+    if (source) *source = plan->source;
+    return MCM_OK;
+}
+
+mcm_status mcm_plan_set_config(mcm_plan *plan, int32_t tile_edge, int32_t pair_min_blocks)
+{
+    if (plan == nullptr || pair_min_blocks < 0) return MCM_ERR_INVALID_ARG;
+    if (tile_edge != 64 && tile_edge != 32) return MCM_ERR_INVALID_ARG;
+    if (plan->count > 0 && !plan->has_var[tile_edge == 32 ? 1 : 0] && !plan->cands.empty())
+        return MCM_ERR_UNSUPPORTED;
+    plan->cfg = PlanConfig{tile_edge, pair_min_blocks};
+    plan->source = MCM_PLAN_TUNED;
+    if (!plan->key.empty()) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[plan->key] = plan->cfg;
+    }
+    return MCM_OK;
+}
+
+mcm_status mcm_plan_candidates(const mcm_plan *plan, int32_t cap, int32_t *tile_edge,
+                               int32_t *pair_min_blocks, float *ms, int32_t *count)
+{
+    if (plan == nullptr || count == nullptr || cap < 0) return MCM_ERR_INVALID_ARG;
+    const int32_t k = (int32_t)plan->cands.size() < cap ? (int32_t)plan->cands.size() : cap;
+    for (int32_t c = 0; c < k; ++c) {
+        if (tile_edge) tile_edge[c] = plan->cands[(size_t)c].T;
+        if (pair_min_blocks) pair_min_blocks[c] = plan->cands[(size_t)c].pair_min;
+        if (ms) ms[c] = plan->cand_ms[(size_t)c];
+    }
+    *count = (int32_t)plan->cands.size();
     return MCM_OK;
 }
 

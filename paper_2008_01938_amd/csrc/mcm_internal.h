@@ -254,6 +254,8 @@ mcm_status run_tiled(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int
 
 // A sequence of tiled launches over several chains.
 struct TiledPlan {
+    int T = 64;                        // tile edge: 64, or 32 (batches of small chains;
+                                       // no optimal-BST weights)
     std::vector<TileChain> chains;
     std::vector<int32_t> NT;           // tiles per side of each chain
     std::vector<TileSeg> segs;
@@ -285,20 +287,21 @@ struct ChainStep {
     BulkLayout cur, next;
 };
 
-int32_t tiled_nt(int32_t n);
+int32_t tiled_nt(int32_t n, int32_t T = 64);
 // Every launch of a lone plan on the caller's stream, in plan order (which
 // already follows every dependency).
 void plan_make_serial(TiledPlan &plan);
 // lone: cus / slots_per_cu describe the device (TiledPlan); else ignored.
-// serial: the launches run alone on the device (every CU free).
-BulkLayout bulk_layout(int32_t NT, int32_t E, int32_t kb, bool lone, int cus = 0,
+// T: tile edge (64 or 32).  serial: the launches run alone on the device
+// (every CU free).
+BulkLayout bulk_layout(int32_t T, int32_t NT, int32_t E, int32_t kb, bool lone, int cus = 0,
                        int slots_per_cu = 0, bool serial = false);
 // Interior cut into `nch` chunks per tile (clamped to [1, kMaxChunks] and
 // to chunks of at least 64 splits), end blocks in chunks of 64 splits.
-BulkLayout bulk_layout_chunks(int32_t NT, int32_t E, int32_t kb, int32_t nch);
+BulkLayout bulk_layout_chunks(int32_t T, int32_t NT, int32_t E, int32_t kb, int32_t nch);
 // Largest partial-minima buffer (uint64) any tile-diagonal of the chain
 // needs under bulk_layout_chunks.
-size_t bulk_part_max(int32_t NT, int32_t kb);
+size_t bulk_part_max(int32_t T, int32_t NT, int32_t kb);
 constexpr int32_t kMaxChunks = 32;
 // Add a chain (offsets as in TileChain); returns its index.
 int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t s_off,
@@ -324,9 +327,10 @@ mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double 
 size_t plan_tables_bytes(const TiledPlan &plan, size_t *seg_offset);
 void plan_tables_write(const TiledPlan &plan, char *dst);
 // run_tiled_plan with the plan's tables already on the device.
+// pair_min_blocks >= 0 overrides the plan's closure-shape threshold.
 mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const TileSeg *segs,
                            const int32_t *p, const double *pd, int64_t *m_all, int32_t *s_all,
                            uint64_t *part_ext, hipStream_t stream,
-                           const ObstWeights *ob = nullptr);
+                           const ObstWeights *ob = nullptr, int pair_min_blocks = -1);
 
 }  // namespace mcm

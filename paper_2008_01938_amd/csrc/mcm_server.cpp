@@ -109,7 +109,7 @@ void layout(Request &r)
     if (r.tiled) {
         int32_t kb = 53 - r.ci.cost_bits;
         if (kb > 20) kb = 20;
-        r.part_half = bulk_part_max(r.NT, kb);
+        r.part_half = bulk_part_max(64, r.NT, kb);
     }
     r.bytes = r.part_at + align_up(2 * r.part_half * sizeof(uint64_t));
 }
@@ -218,7 +218,7 @@ bool Server::launch_iteration()
             nch = (int32_t)((share + tiles - 1.0) / tiles);
         }
         cs.cur = r->lay;
-        cs.next = bulk_layout_chunks(r->NT, E, plan.chains[cs.chain].kb, nch);
+        cs.next = bulk_layout_chunks(64, r->NT, E, plan.chains[cs.chain].kb, nch);
         r->lay_next = cs.next;
         steps.push_back(cs);
     }

@@ -207,13 +207,16 @@ static void check_plan(const TiledPlan &plan, int T, const char *what)
 
 static void check_lone_plans()
 {
-    const int T = 64;
-    const int ns[] = {1, 2, 63, 64, 65, 128, 129, 191, 193, 300, 1000, 2048, 3001, 8192, 16384};
+    const int ns[] = {1, 2, 31, 32, 33, 63, 64, 65, 128, 129, 191, 193, 300, 1000, 2048, 3001,
+                      8192, 16384};
+    for (int T : {64, 32})
     for (int n : ns) {
+        if (T == 32 && n > 3001) continue;
         for (int mode = 0; mode < 4; ++mode) {
             ChainInfo ci;
             CHECK(chain_bound(n, 1024, &ci) == MCM_OK);
             TiledPlan plan;
+            plan.T = T;
             plan.lone = mode != 3;
             plan.serial = mode == 1;
             plan.chunk_target = mode == 2 ? 512 : 0;
@@ -223,7 +226,7 @@ static void check_lone_plans()
             plan_lockstep(plan, {c});
             if (plan.serial) plan_make_serial(plan);
             char what[64];
-            snprintf(what, sizeof what, "lone n=%d mode=%d", n, mode);
+            snprintf(what, sizeof what, "lone n=%d mode=%d T=%d", n, mode, T);
             check_plan(plan, T, what);
             size_t seg_off = 0;
             const size_t bytes = plan_tables_bytes(plan, &seg_off);
@@ -238,10 +241,11 @@ static void check_lone_plans()
 static void check_batch_plans()
 {
     std::mt19937_64 rng(3);
-    for (int trial = 0; trial < 6; ++trial) {
+    for (int trial = 0; trial < 12; ++trial) {
         TiledPlan plan;
+        plan.T = trial % 2 ? 32 : 64;
         std::vector<int> ids;
-        const int count = trial == 5 ? 4096 : 1 + (int)(rng() % 300);
+        const int count = trial >= 10 ? 4096 : 1 + (int)(rng() % 300);
         int64_t off = 0;
         for (int b = 0; b < count; ++b) {
             const int n = 16 + (int)(rng() % 497);
@@ -252,8 +256,8 @@ static void check_batch_plans()
         }
         plan_lockstep(plan, ids);
         char what[64];
-        snprintf(what, sizeof what, "batch trial %d count %d", trial, count);
-        check_plan(plan, 64, what);
+        snprintf(what, sizeof what, "batch trial %d count %d T %d", trial, count, plan.T);
+        check_plan(plan, plan.T, what);
     }
 }
 
