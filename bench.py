@@ -453,23 +453,28 @@ def bench_serving(binding, workloads, torch, count: int, load: float):
                          "p99_speedup_vs_plain": over_plain["p99_ms"] / over_served["p99_ms"]}}
 
 
-def counter_probe(binding, workloads, torch, chain, m, s, batched: bool = True):
-    """For rocprofv3 counter runs: one n = 8192 solve on the serial schedule
-    (every launch alone on the device), one plan solve of the 4096-chain
-    batch, then a plain device copy of a known size (the counters' scale)."""
-    binding.profile_enable(True, classes=[], serial=True)
-    chain.solve_into(m, s)
-    torch.cuda.synchronize()
-    binding.profile_enable(False)
-    if batched:
+def counter_probe(binding, workloads, torch, chain, m, s, which: str):
+    """For rocprofv3 counter runs, one workload per process so that every
+    kernel's dispatches belong to it: `single`, one n = 8192 solve on the
+    serial schedule (every launch alone on the device); `batched`, one plan
+    solve of the 4096-chain batch on 64-edge tiles, then one on 32-edge
+    tiles.  Then a plain device copy of a known size (the counters' scale)."""
+    if which == "single":
+        binding.profile_enable(True, classes=[], serial=True)
+        chain.solve_into(m, s)
+        torch.cuda.synchronize()
+        binding.profile_enable(False)
+    else:
         b = workloads.batched_4096()
         off = binding.table_offsets(b.ns)
         total = int(off[-1] + int(b.ns[-1]) ** 2)
         m_all = torch.empty(total, dtype=torch.int64, device="cuda")
         s_all = torch.empty(total, dtype=torch.int32, device="cuda")
         plan = binding.Plan(b.ns, b.p_off, off, int(b.p_all.max()))
-        plan.solve_into(b.p_all, m_all, s_all)
-        torch.cuda.synchronize()
+        for edge in (64, 32):
+            plan.set_config(edge)
+            plan.solve_into(b.p_all, m_all, s_all)
+            torch.cuda.synchronize()
         plan.close()
         del m_all, s_all
     nbytes = 1 << 30
@@ -478,7 +483,7 @@ def counter_probe(binding, workloads, torch, chain, m, s, batched: bool = True):
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"counter_probe": True, "copy_bytes": nbytes, "batched": batched,
+    print(json.dumps({"counter_probe": which, "copy_bytes": nbytes,
                       "kernel_source_sha256": source_sha()}), flush=True)
 
 
@@ -491,9 +496,10 @@ def main() -> int:
     ap.add_argument("--algo", default="auto", choices=["auto", "tiled", "wavefront"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall time target of the CPU-baseline sample (0 = skip)")
-    ap.add_argument("--counter-probe", action="store_true",
-                    help="one serial-schedule solve, one batched plan solve and a 1 GiB "
-                         "copy, for rocprofv3 counter runs")
+    ap.add_argument("--counter-probe", choices=["single", "batched"],
+                    help="for rocprofv3 counter runs: one n=8192 solve on the serial "
+                         "schedule (single) or the 4096-chain batch on 64- and 32-edge tiles "
+                         "(batched), then a 1 GiB copy")
     ap.add_argument("--no-small", action="store_true", help="skip the n=128 / n=2048 section")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
@@ -538,7 +544,7 @@ def main() -> int:
     torch.cuda.synchronize()
 
     if args.counter_probe:
-        counter_probe(binding, workloads, torch, chain, m, s, batched=not args.no_batched)
+        counter_probe(binding, workloads, torch, chain, m, s, args.counter_probe)
         return 0
 
     for _ in range(args.warmup):

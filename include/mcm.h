@@ -59,7 +59,7 @@ typedef enum mcm_status {
 /*
  * Kernel paths.  All produce identical bytes; they differ in speed and in
  * the inputs they accept.
- *   MCM_ALGO_AUTO       pick the fastest path that accepts the input.
+ *   MCM_ALGO_AUTO       pick the fastest path for the input (the tiled path).
  *   MCM_ALGO_WAVEFRONT  one launch per diagonal of the table; every cell of
  *                       a diagonal is independent (Fig. 5 order), its splits
  *                       are scanned by a group of lanes and reduced in
@@ -68,9 +68,12 @@ typedef enum mcm_status {
  *   MCM_ALGO_TILED      T x T tiles of the table in tile-diagonal order;
  *                       operand panels staged through LDS and reused across
  *                       a register microtile; split range spread over
- *                       workgroups; a per-tile closure pass in LDS.  Exact
- *                       integers carried in fp64; accepts inputs with
- *                       (n-1) * max(p)^3 < 2^46 (else MCM_ERR_UNSUPPORTED).
+ *                       workgroups; a per-tile closure pass in LDS.  When
+ *                       (n-1) * max(p)^3 < 2^46, exact integers carried in
+ *                       fp64 keys (cost * 2^kb + local split: one fma, add
+ *                       and min per split); beyond that, up to the int64
+ *                       limit, the same schedule on int64 costs with the
+ *                       split carried apart.  Accepts every valid input.
  *   MCM_ALGO_PIPELINE   the paper's pipeline (Section IV-B, Fig. 8): the
  *                       table linearised in diagonal order, thread j folding
  *                       split j of an element one step after thread j-1, a
@@ -129,8 +132,8 @@ mcm_status mcm_solve_algo(const int32_t *p, int32_t n, int64_t *m_out, int32_t *
  * Many independent chains in one call.  All chains advance together, one
  * tile-diagonal per iteration, each kernel launch serving every chain that
  * is still active, so a batch of thousands of small chains costs a few
- * dozen launches instead of thousands.  Chains outside the fp64-exact range
- * of the tiled path are solved with the int64 wavefront.
+ * dozen launches instead of thousands.  Chains beyond the fp64 keys' exact
+ * range run the tiled path's int64 kernels, after the others.
  *   count   number of chains (>= 0; 0 is a no-op).
  *   n       host, count entries: matrices of chain b (>= 1).
  *   p_off   host, count entries: chain b's dims are p_all[p_off[b] ..
@@ -158,7 +161,7 @@ mcm_status mcm_solve_batched(int32_t count, const int32_t *n, const int64_t *p_o
  *                     dimension the plan will be solved with (the tiled
  *                     path's exact key width is sized for it, so a chain
  *                     whose (n-1) * max_dim^3 exceeds that range takes the
- *                     int64 wavefront).  Validates the shape (INVALID_ARG,
+ *                     int64 tiled kernels).  Validates the shape (INVALID_ARG,
  *                     OVERFLOW as mcm_check_chain with every dim = max_dim)
  *                     before any HIP call, then allocates and copies the
  *                     tables synchronously on the current device.  *out

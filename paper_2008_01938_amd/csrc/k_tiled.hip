@@ -501,43 +501,67 @@ struct CloseRegs {
         Xrow[CloseShape<T, G>::CS];
 };
 
+// Minimum of v[Lo..Hi) as a balanced tree (Hi > Lo, both compile-time).
+template <int Lo, int Hi>
+__device__ __forceinline__ double range_min(const double *v)
+{
+    if constexpr (Hi - Lo == 1) {
+        return v[Lo];
+    } else {
+        constexpr int M = (Lo + Hi) / 2;
+        return fmin(range_min<Lo, M>(v), range_min<M, Hi>(v));
+    }
+}
+
 // One step of a row group: the minimum over its (a) and (b) splits of cell
-// (r, cc).  Every (b) slot is read: a slot whose cell is not final yet still
-// holds Xrow = 2^62, so whatever DJ value it meets, its term loses.
-template <int T, int G, int T0, class Lds>  // T0: first (a) slot any row of this wave uses
+// (r, cc).  T0: the first (a) slot any row of the wave uses; TB: the (b)
+// slots any row of the wave can use (c' < c for its largest c).  A (b) slot
+// inside that bound whose cell is not final yet still holds Xrow = 2^62, so
+// whatever DJ value it meets, its term loses.
+template <int T, int G, int T0, int TB, class Lds>
 __device__ __forceinline__ double close_step(const CloseRegs<T, G> &R, const Lds &L, int xo,
                                              int djb, int g, double pJc)
 {
     constexpr int CS = CloseShape<T, G>::CS;
-    double xa[CS], xb[CS];
+    double xa[CS], xb[CS], va[CS], vb[CS];
     const double *__restrict__ xcol = &L.Xt[0][0] + xo;  // column cc of Xt
 #pragma unroll
     for (int t = T0; t < CS; ++t) xa[t] = xcol[t * G + g + 1];
 #pragma unroll
-    for (int t = 0; t < CS; ++t) xb[t] = L.dj_at_base(djb, t * G + g);
-    // Independent terms, then a balanced min tree.
-    double v[CS];
+    for (int t = 0; t < TB; ++t) xb[t] = L.dj_at_base(djb, t * G + g);
+    // Independent terms, then balanced min trees.
 #pragma unroll
-    for (int t = 0; t < CS; ++t) {
-        const double tb = fma(pJc, R.PJr[t], xb[t]) + R.Xrow[t];
-        v[t] = t >= T0 ? fmin(tb, fma(pJc, R.PIr[t], R.DIr[t]) + xa[t]) : tb;
-    }
+    for (int t = T0; t < CS; ++t) va[t] = fma(pJc, R.PIr[t], R.DIr[t]) + xa[t];
 #pragma unroll
-    for (int span = 1; span < CS; span *= 2)
-#pragma unroll
-        for (int t = 0; t + span < CS; t += 2 * span) v[t] = fmin(v[t], v[t + span]);
-    return min_group<G>(v[0]);
+    for (int t = 0; t < TB; ++t) vb[t] = fma(pJc, R.PJr[t], xb[t]) + R.Xrow[t];
+    double v;
+    if constexpr (TB == 0)
+        v = range_min<T0, CS>(va);
+    else
+        v = fmin(range_min<T0, CS>(va), range_min<0, TB>(vb));
+    return min_group<G>(v);
 }
 
-// close_step with its first (a) slot t0 (wave-uniform) as a template argument.
-template <int T, int G, int T0, class Lds>
-__device__ __forceinline__ double close_step_at(int t0, const CloseRegs<T, G> &R, const Lds &L,
+// close_step with its slot bounds t0 and tb (wave-uniform) as template
+// arguments.
+template <int T, int G, int T0, int TB, class Lds>
+__device__ __forceinline__ double close_step_tb(int tb, const CloseRegs<T, G> &R, const Lds &L,
                                                 int xo, int djb, int g, double pJc)
 {
-    if constexpr (T0 + 1 < CloseShape<T, G>::CS) {
-        if (t0 > T0) return close_step_at<T, G, T0 + 1>(t0, R, L, xo, djb, g, pJc);
+    if constexpr (TB + 1 <= CloseShape<T, G>::CS) {
+        if (tb > TB) return close_step_tb<T, G, T0, TB + 1>(tb, R, L, xo, djb, g, pJc);
     }
-    return close_step<T, G, T0>(R, L, xo, djb, g, pJc);
+    return close_step<T, G, T0, TB>(R, L, xo, djb, g, pJc);
+}
+
+template <int T, int G, int T0, class Lds>
+__device__ __forceinline__ double close_step_at(int t0, int tb, const CloseRegs<T, G> &R,
+                                                const Lds &L, int xo, int djb, int g, double pJc)
+{
+    if constexpr (T0 + 1 < CloseShape<T, G>::CS) {
+        if (t0 > T0) return close_step_at<T, G, T0 + 1>(t0, tb, R, L, xo, djb, g, pJc);
+    }
+    return close_step_tb<T, G, T0, 0>(tb, R, L, xo, djb, g, pJc);
 }
 
 // OB: the optimal-BST weights (pd_all then holds zeros, so every product
@@ -692,7 +716,11 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
             }
             const double pJc = L.pJs[cc + 1];
             const double xbulk = (&L.Xt[0][0])[xo + r];
-            const double best = close_step_at<T, G, 0>((h * CROWS) / G, R, L, xo, djb, g, pJc);
+            // (b) slots the wave's rows can use: c' < c for its last row's c.
+            const int c_top = min(c_hi, nJ - 1);
+            const int tb = c_top >= 1 ? min(CS, (c_top - 1) / G + 1) : 0;
+            const double best =
+                close_step_at<T, G, 0>((h * CROWS) / G, tb, R, L, xo, djb, g, pJc);
             const double fin = fmin(best, xbulk);
             const double base = floor(fin * inv_scale);
             const double cost = OB ? base + (pJc - w_row) : base;
@@ -787,6 +815,319 @@ static_assert(2 * sizeof(CloseLdsPacked<64>) <= 163840, "two paired closures per
 constexpr size_t kCloseExtraLds =
     163840 - sizeof(CloseLdsFull<64>) - sizeof(BulkLds<64>) + 1024;
 static_assert(sizeof(CloseLdsFull<64>) + kCloseExtraLds <= 163840, "closure LDS exceeds a CU");
+
+// ------------------------------------------------------------------------
+// Exact int64 arithmetic for chains beyond the fp64 keys' range
+// ((n-1) max(p)^3 >= 2^46, up to the int64 limit): the same decomposition,
+// chunking and schedule on 64-edge tiles, with costs and splits carried
+// apart and compared as (cost, split) pairs.  Every sum formed is a real
+// candidate cost (< 2^63 by the host's bound), so nothing can overflow:
+// splits that do not apply are skipped, never padded.  The diagonal tiles
+// use k_tri<64, false>.  Partial minima take two words per cell: the cost
+// block (T*T int64) of a slot, then its split block.
+// ------------------------------------------------------------------------
+constexpr int WT = 64;
+
+struct BulkLdsWide {
+    int64_t As[2][KC][WT + 1];  // m[row0+r][k]
+    int64_t Bs[2][KC][WT];      // m[k+1][col0+c]
+    int64_t Ps[2][KC];          // p[k+1]
+};
+
+__global__ __launch_bounds__(256) void k_bulk_wide(const TileChain *__restrict__ chains,
+                                                  const TileSeg *__restrict__ segs, int nseg,
+                                                  const int64_t *__restrict__ m_all,
+                                                  const int32_t *__restrict__ p_all,
+                                                  int64_t *__restrict__ part_all)
+{
+    constexpr int T = WT, TW = 16, RA = 16, RB = 4, V = 4;
+    __shared__ BulkLdsWide L;
+    const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
+    const TileChain ch = chains[sg.chain];
+    const int local = blockIdx.x - sg.first;
+    const int32_t n = ch.n, D = sg.D, KS = sg.KS;
+    const int64_t *__restrict__ m = m_all + ch.m_off;
+    const int32_t *__restrict__ p = p_all + ch.p_off;
+    const int tid = threadIdx.x;
+    const int tile = local / sg.nch;
+    const int chunk = local - tile * sg.nch;
+    const int I = tile, J = tile + D;
+    const int row0 = I * T, col0 = J * T;
+    const int kbase = (I + 1) * T - 1 + sg.koff;
+    const int k0 = kbase + chunk * KS;
+    const int kend = min(k0 + KS, kbase + sg.klen);  // exclusive
+    const int rounds = (kend - k0 + KC - 1) / KC;
+    const int nJ = min(T, n - col0);
+    const int tx = tid % TW, ty = tid / TW;
+
+    int64_t pj[4][4], best[4][4];
+    int32_t bk[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int64_t pi = p[row0 + ty + TW * a];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int c = tx + TW * b;
+            pj[a][b] = c < nJ ? pi * (int64_t)p[col0 + c + 1] : 0;
+            best[a][b] = INT64_MAX;
+            bk[a][b] = k0;
+        }
+    }
+    // Staging as in k_bulk; splits at or past kend are staged from kend-1
+    // (inside the table) and never evaluated.
+    const int akk = tid % KC, ar = tid / KC;
+    const int bcol = tid % T, bc = min(bcol, nJ - 1), bkk = tid / T;
+    int64_t ra[V], rb[V], rp = 0;
+    auto load = [&](int kc) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int ka = min(kc + akk, kend - 1);
+            ra[v] = m[(size_t)(row0 + ar + RA * v) * n + ka];
+            const int kb2 = min(kc + bkk + RB * v, kend - 1);
+            rb[v] = m[(size_t)(kb2 + 1) * n + col0 + bc];
+        }
+        if (tid < KC) rp = p[min(kc + tid, kend - 1) + 1];
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            L.As[buf][akk][ar + RA * v] = ra[v];
+            L.Bs[buf][bkk + RB * v][bcol] = rb[v];
+        }
+        if (tid < KC) L.Ps[buf][tid] = rp;
+    };
+
+    load(k0);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int rd = 0; rd < rounds; ++rd) {
+        const int kc = k0 + rd * KC;
+        const bool more = rd + 1 < rounds;
+        const int kn = min(KC, kend - kc);  // splits of this round (uniform)
+        if (more) load(kc + KC);
+        for (int kk = 0; kk < kn; ++kk) {
+            int64_t av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = L.As[buf][kk][ty + TW * a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = L.Bs[buf][kk][tx + TW * b];
+            const int64_t pk = L.Ps[buf][kk];
+            // Splits arrive in increasing k, so a strict < keeps the smallest.
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int64_t c = pj[a][b] * pk + bv[b] + av[a];
+                    if (c < best[a][b]) {
+                        best[a][b] = c;
+                        bk[a][b] = kc + kk;
+                    }
+                }
+        }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+
+    int64_t *out = part_all + sg.part_off + ((size_t)tile * sg.PT + sg.slot0 + chunk) * 2 * T * T;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int r = ty + TW * a, c = tx + TW * b;
+            out[r * T + c] = c < nJ ? best[a][b] : INT64_MAX;
+            out[T * T + r * T + c] = bk[a][b];
+        }
+    }
+}
+
+// (cost, split) pair order: the smaller cost, then the smaller split.
+__device__ __forceinline__ bool pair_less(int64_t c1, int32_t k1, int64_t c0, int32_t k0)
+{
+    return c1 < c0 || (c1 == c0 && k1 < k0);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void dpp_pair_min(int64_t &c, int32_t &k)
+{
+    const int2 b = __builtin_bit_cast(int2, c);
+    int2 o;
+    o.x = __builtin_amdgcn_mov_dpp(b.x, CTRL, 0xF, 0xF, false);
+    o.y = __builtin_amdgcn_mov_dpp(b.y, CTRL, 0xF, 0xF, false);
+    const int32_t ok = __builtin_amdgcn_mov_dpp(k, CTRL, 0xF, 0xF, false);
+    const int64_t oc = __builtin_bit_cast(int64_t, o);
+    if (pair_less(oc, ok, c, k)) {
+        c = oc;
+        k = ok;
+    }
+}
+
+struct CloseLdsWide {
+    int64_t DJ[WT][WT + 1];  // DJ[c][q] = m[col0+q][col0+c] (1 <= q <= c)
+    int64_t X[WT][WT + 1];   // X[c][q]: bulk minimum, then final cost of cell (q, c)
+    int32_t K[WT][WT + 1];   // its split
+    int64_t pJ[WT + 1];      // p[col0 + q]
+};
+
+// The closure of one 64-edge tile on int64: row group r (16 lanes) sweeps
+// its row in local anti-diagonal order as in close_tile.  A lane scans its
+// (a) splits, then (lane 0) the bulk minimum, then its (b) splits, in
+// increasing split order with a strict <, so its pair is the lexicographic
+// minimum of its splits; four DPP steps combine the 16 lanes.
+__global__ __launch_bounds__(1024) void k_close_wide(const TileChain *__restrict__ chains,
+                                                    const TileSeg *__restrict__ segs, int nseg,
+                                                    int64_t *__restrict__ m_all,
+                                                    int32_t *__restrict__ s_all,
+                                                    const int32_t *__restrict__ p_all,
+                                                    const int64_t *__restrict__ part_all)
+{
+    constexpr int T = WT, G = 16, CS = T / G, CTH = T * G, CROWS = 64 / G;
+    __shared__ CloseLdsWide L;
+    const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
+    const TileChain ch = chains[sg.chain];
+    const int local = blockIdx.x - sg.first;
+    const int tid = threadIdx.x;
+    const int32_t n = ch.n, D = sg.D, PT = sg.PT;
+    int64_t *__restrict__ m = m_all + ch.m_off;
+    int32_t *__restrict__ s = s_all + ch.s_off;
+    const int32_t *__restrict__ p = p_all + ch.p_off;
+    const int64_t *__restrict__ part = part_all + sg.part_off;
+    const int I = local, J = I + D;
+    const int row0 = I * T, col0 = J * T;
+    const int nJ = min(T, n - col0);
+    const int r = tid / G, g = tid % G;
+    const int h = __builtin_amdgcn_readfirstlane(tid / 64);
+
+    // Lane g of row r holds the (a) splits q = t*G + g (r <= q <= T-2) and
+    // the (b) splits c' = t*G + g.
+    int64_t DIr[CS], PIr[CS], PJr[CS], Xrow[CS];
+    const int64_t pi = p[row0 + r];
+#pragma unroll
+    for (int t = 0; t < CS; ++t) {
+        const int q = t * G + g;
+        const bool qa = q >= r && q <= T - 2;
+        DIr[t] = qa ? m[(size_t)(row0 + r) * n + row0 + q] : 0;
+        PIr[t] = qa ? pi * (int64_t)p[row0 + q + 1] : 0;
+        PJr[t] = q < nJ ? pi * (int64_t)p[col0 + q + 1] : 0;
+        Xrow[t] = 0;
+    }
+    for (int q = tid; q <= T; q += CTH) L.pJ[q] = q <= nJ ? p[col0 + q] : 0;
+    for (int idx = tid; idx < T * T; idx += CTH) {
+        const int qq = idx / T, c = idx % T;
+        if (qq >= 1 && qq <= c && c < nJ) L.DJ[c][qq] = m[(size_t)(col0 + qq) * n + col0 + c];
+    }
+    // Bulk minimum per cell: the lexicographic minimum of the PT partial
+    // pairs, or for D == 1 the single split k = (I+1)T-1.
+    constexpr int CPT = T * T / CTH;
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int idx = tid + CTH * u;
+        const int rr = idx / T, c = idx % T;
+        int64_t bc = INT64_MAX;
+        int32_t bkk = INT32_MAX;
+        if (c < nJ) {
+            if (D == 1) {
+                const int k = row0 + T - 1;
+                bc = m[(size_t)(row0 + rr) * n + k] + m[(size_t)(k + 1) * n + col0 + c] +
+                     (int64_t)p[row0 + rr] * (int64_t)p[k + 1] * (int64_t)p[col0 + c + 1];
+                bkk = k;
+            } else {
+                const int64_t *src = part + (size_t)I * PT * 2 * T * T;
+                for (int sl = 0; sl < PT; ++sl) {
+                    const int64_t pc = src[(size_t)sl * 2 * T * T + idx];
+                    const int32_t pk = (int32_t)src[(size_t)sl * 2 * T * T + T * T + idx];
+                    if (pair_less(pc, pk, bc, bkk)) {
+                        bc = pc;
+                        bkk = pk;
+                    }
+                }
+            }
+            L.X[c][rr] = bc;
+            L.K[c][rr] = bkk;
+        }
+    }
+    __syncthreads();
+
+    __builtin_amdgcn_s_setprio(3);
+    const int wmax = (T - 1) + (nJ - 1);
+    for (int w = 0; w <= wmax; ++w) {
+        const int c = w - (T - 1 - r);
+        const int c_lo = w - (T - 1 - CROWS * h);
+        const int c_hi = c_lo + CROWS - 1;
+        if (c_hi >= 0 && c_lo < nJ) {  // wave-uniform
+            const int cc = min(max(c, 0), nJ - 1);
+            const int64_t pJc = L.pJ[cc + 1];
+            int64_t best = INT64_MAX;
+            int32_t bk = INT32_MAX;
+#pragma unroll
+            for (int t = 0; t < CS; ++t) {  // (a): k = row0 + q, increasing in t
+                const int q = t * G + g;
+                if (q >= r && q <= T - 2) {
+                    const int64_t v = DIr[t] + L.X[cc][q + 1] + PIr[t] * pJc;
+                    if (v < best) {
+                        best = v;
+                        bk = row0 + q;
+                    }
+                }
+            }
+            if (g == 0) {  // the bulk splits lie between (a) and (b)
+                const int64_t v = L.X[cc][r];
+                if (v < best) {
+                    best = v;
+                    bk = L.K[cc][r];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < CS; ++t) {  // (b): k = col0 + c', increasing in t
+                const int cp = t * G + g;
+                if (cp < cc) {
+                    const int64_t v = Xrow[t] + L.DJ[cc][cp + 1] + PJr[t] * pJc;
+                    if (v < best) {
+                        best = v;
+                        bk = col0 + cp;
+                    }
+                }
+            }
+            dpp_pair_min<0xB1>(best, bk);   // lane ^ 1
+            dpp_pair_min<0x4E>(best, bk);   // lane ^ 2
+            dpp_pair_min<0x141>(best, bk);  // i <-> 7 - i
+            dpp_pair_min<0x140>(best, bk);  // i <-> 15 - i
+            if (c >= 0 && c < nJ) {
+#pragma unroll
+                for (int t = 0; t < CS; ++t)
+                    if (t * G + g == c) Xrow[t] = best;
+                if (g == 0) {
+                    L.X[c][r] = best;
+                    L.K[c][r] = bk;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    for (int idx = tid; idx < T * T; idx += CTH) {
+        const int rr = idx / T, c = idx % T;
+        if (c < nJ) {
+            const size_t o = (size_t)(row0 + rr) * n + col0 + c;
+            m[o] = L.X[c][rr];
+            s[o] = L.K[c][rr];
+        }
+    }
+    for (int idx = tid; idx < T * T; idx += CTH) {
+        const int c = idx / T, rr = idx % T;
+        if (c < nJ) {
+            const size_t o = (size_t)(col0 + c) * n + row0 + rr;
+            m[o] = L.X[c][rr];
+            s[o] = -1;
+        }
+    }
+}
+
+// The same reservation for the int64 closure of a lone chain.
+constexpr size_t kCloseWideExtraLds =
+    163840 - sizeof(CloseLdsWide) - sizeof(BulkLdsWide) + 1024;
+static_assert(sizeof(CloseLdsWide) + kCloseWideExtraLds <= 163840, "closure LDS exceeds a CU");
 
 // A bounded pause (constant-rate wall clock) on the stream it runs on.
 __global__ __launch_bounds__(64) void k_delay(long long ticks)
@@ -1024,8 +1365,10 @@ int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t 
     c.p_off = p_off;
     c.pd_off = pd_off;
     c.n = ci.n;
-    c.kb = 53 - ci.cost_bits;
-    if (c.kb > 20) c.kb = 20;
+    // fp64 keys: bits below the cost.  The int64 kernels carry splits apart,
+    // so a chunk's split count is not bounded by key bits there.
+    c.kb = plan.wide ? 30 : 53 - ci.cost_bits;
+    if (!plan.wide && c.kb > 20) c.kb = 20;
     c.kbits = bitlen_u64((uint64_t)(ci.n > 1 ? ci.n - 1 : 1));
     plan.chains.push_back(c);
     plan.NT.push_back(tiled_nt(ci.n, plan.T));
@@ -1180,8 +1523,10 @@ void plan_lockstep(TiledPlan &plan, const std::vector<int> &ids)
     };
     std::vector<const std::vector<BulkLayout> *> lay(ids.size());
     for (size_t u = 0; u < ids.size(); ++u) lay[u] = &layouts(ids[u]);
+    // The int64 kernels keep two words (cost, split) per partial minimum.
+    const size_t words = plan.wide ? 2 : 1;
     auto elems = [&](size_t u, int E) {
-        return E < (int)lay[u]->size() ? (*lay[u])[E].elems : (size_t)0;
+        return E < (int)lay[u]->size() ? words * (*lay[u])[E].elems : (size_t)0;
     };
     size_t half = 0;
     for (int E = 2; E < maxNT; ++E) {
@@ -1298,7 +1643,21 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
             break;
         }
         const TileSeg *sg = segs + L.seg_begin;
-        if (L.kind == TK_TRI) {
+        if (plan.wide) {
+            ProfileScope ps(L.kind == TK_TRI ? KC_SETUP : L.kind == TK_BULK ? KC_BULK : KC_CLOSE,
+                            q, L.evals);
+            if (L.kind == TK_TRI)
+                hipLaunchKernelGGL((k_tri<64, false>), dim3(L.blocks), dim3(NTH), 0, q, chains,
+                                   sg, L.nseg, p, m_all, s_all, nullptr, nullptr, nullptr);
+            else if (L.kind == TK_BULK)
+                hipLaunchKernelGGL(k_bulk_wide, dim3(L.blocks), dim3(256), 0, q, chains, sg,
+                                   L.nseg, m_all, p, (int64_t *)part);
+            else
+                hipLaunchKernelGGL(k_close_wide, dim3(L.blocks), dim3(1024),
+                                   plan.lone ? kCloseWideExtraLds : 0, q, chains, sg, L.nseg,
+                                   m_all, s_all, p, (const int64_t *)part);
+            e = hipGetLastError();
+        } else if (L.kind == TK_TRI) {
             ProfileScope ps(KC_SETUP, q, L.evals);
             if (ob)
                 hipLaunchKernelGGL((k_tri<64, true>), dim3(L.blocks), dim3(NTH), 0, q, chains, sg,
@@ -1385,8 +1744,8 @@ void plan_make_serial(TiledPlan &plan)
 mcm_status run_tiled(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int32_t *s,
                      hipStream_t stream)
 {
-    if (!tiled_accepts(ci)) return MCM_ERR_UNSUPPORTED;
     TiledPlan plan;
+    plan.wide = !tiled_accepts(ci);
     plan.lone = true;
     plan.serial = profile_serial();
     plan.cus = device_cus();

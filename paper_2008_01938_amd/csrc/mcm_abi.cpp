@@ -442,7 +442,7 @@ int32_t mcm_select_algo(const int32_t *p, int32_t n)
     ChainInfo ci;
     mcm_status st = check_chain(p, n, &ci);
     if (st != MCM_OK) return -(int32_t)st;
-    return tiled_accepts(ci) ? MCM_ALGO_TILED : MCM_ALGO_WAVEFRONT;
+    return MCM_ALGO_TILED;
 }
 
 }  // extern "C"
@@ -454,10 +454,9 @@ mcm_status check_outputs(const ChainInfo &ci, int64_t *m_out, int32_t *s_out, in
 {
     if (m_out == nullptr || s_out == nullptr) return MCM_ERR_INVALID_ARG;
     if (((uintptr_t)m_out & 7) != 0 || ((uintptr_t)s_out & 3) != 0) return MCM_ERR_INVALID_ARG;
-    if (*algo == MCM_ALGO_AUTO) *algo = tiled_accepts(ci) ? MCM_ALGO_TILED : MCM_ALGO_WAVEFRONT;
+    if (*algo == MCM_ALGO_AUTO) *algo = MCM_ALGO_TILED;
     if (*algo != MCM_ALGO_WAVEFRONT && *algo != MCM_ALGO_TILED && *algo != MCM_ALGO_PIPELINE)
         return MCM_ERR_INVALID_ARG;
-    if (*algo == MCM_ALGO_TILED && !tiled_accepts(ci)) return MCM_ERR_UNSUPPORTED;
     if (*algo == MCM_ALGO_PIPELINE && ci.n > kPipeMaxN) return MCM_ERR_UNSUPPORTED;
     return MCM_OK;
 }
@@ -542,7 +541,8 @@ struct mcm_plan {
     std::vector<int32_t> n;
     std::vector<int64_t> p_off, tab_off;
     std::vector<ChainInfo> ci;     // per chain, from n and max_dim
-    std::vector<int32_t> wavefront;  // chains outside the tiled range
+    PlanVariant wide;               // chains beyond the fp64 keys' range: int64 kernels
+    bool has_wide = false;
     int64_t p_len = 0;              // dims read: p_all[0 .. p_len)
     PlanVariant var[2];             // [0]: 64-edge tiles; [1]: 32-edge tiles (small chains only)
     bool has_var[2] = {false, false};
@@ -555,6 +555,7 @@ struct mcm_plan {
     {
         for (PlanVariant &v : var)
             if (v.tables) (void)hipFree(v.tables);
+        if (wide.tables) (void)hipFree(wide.tables);
     }
 };
 
@@ -646,12 +647,17 @@ mcm_status mcm_solve_batched(int32_t count, const int32_t *n, const int64_t *p_o
     }
     plan_lockstep(plan, ids);
     st = run_tiled_plan(plan, p_dev, pd_dev, m_all, s_all, nullptr, stream);
-    for (int32_t b = 0; b < count && st == MCM_OK; ++b) {
+    // Chains beyond the fp64 keys' range: the int64 tiled kernels, after.
+    TiledPlan wide;
+    wide.wide = true;
+    std::vector<int> wids;
+    for (int32_t b = 0; b < count; ++b) {
         if (tiled_accepts(ci[b])) continue;
-        DeviceChain dc;
-        dc.p = p_dev + p_off[b];
-        dc.pd = pd_dev + p_off[b];
-        st = run_wavefront(dc, ci[b], m_all + tab_off[b], s_all + tab_off[b], stream);
+        wids.push_back(plan_add_chain(wide, ci[b], tab_off[b], tab_off[b], p_off[b], p_off[b]));
+    }
+    if (st == MCM_OK && !wids.empty()) {
+        plan_lockstep(wide, wids);
+        st = run_tiled_plan(wide, p_dev, pd_dev, m_all, s_all, nullptr, stream);
     }
     ws_free(pd_own, stream);
     ws_free(dev, stream);
@@ -682,11 +688,11 @@ mcm_status mcm_plan_create(int32_t count, const int32_t *n, const int64_t *p_off
     if (!ranges_disjoint(count, n, tab_off, true)) return MCM_ERR_INVALID_ARG;
     if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
     if (hipGetDevice(&pl->device) != hipSuccess) return MCM_ERR_DEVICE;
-    std::vector<int32_t> tiled;
+    std::vector<int32_t> tiled, wide_ids;
     int32_t max_n = 1;
     for (int32_t b = 0; b < count; ++b) {
         if (!tiled_accepts(pl->ci[b])) {
-            pl->wavefront.push_back(b);
+            wide_ids.push_back(b);
             continue;
         }
         tiled.push_back(b);
@@ -713,6 +719,25 @@ mcm_status mcm_plan_create(int32_t count, const int32_t *n, const int64_t *p_off
         }
         if (hipMemcpy(pv.tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
             return MCM_ERR_DEVICE;
+    }
+    if (!wide_ids.empty()) {
+        PlanVariant &pv = pl->wide;
+        pv.tp.wide = true;
+        std::vector<int> ids;
+        for (int32_t b : wide_ids)
+            ids.push_back(plan_add_chain(pv.tp, pl->ci[b], tab_off[b], tab_off[b], p_off[b],
+                                         p_off[b]));
+        plan_lockstep(pv.tp, ids);
+        const size_t bytes = plan_tables_bytes(pv.tp, &pv.seg_off);
+        std::vector<char> host(bytes);
+        plan_tables_write(pv.tp, host.data());
+        if (hipMalloc(&pv.tables, bytes) != hipSuccess) {
+            pv.tables = nullptr;
+            return MCM_ERR_NO_MEMORY;
+        }
+        if (hipMemcpy(pv.tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return MCM_ERR_DEVICE;
+        pl->has_wide = true;
     }
     // Candidates: 64-edge tiles at four closure-shape thresholds, then
     // 32-edge tiles.
@@ -777,13 +802,10 @@ mcm_status plan_solve(const mcm_plan *pl, const int32_t *p_all, int64_t *m_all, 
         st = exec_tiled_plan(pv.tp, (const TileChain *)pv.tables,
                              (const TileSeg *)((const char *)pv.tables + pv.seg_off), p_dev, pd,
                              m_all, s_all, nullptr, stream, nullptr, cfg.pair_min);
-    for (size_t u = 0; u < pl->wavefront.size() && st == MCM_OK; ++u) {
-        const int32_t b = pl->wavefront[u];
-        DeviceChain dc;
-        dc.p = p_dev + pl->p_off[b];
-        dc.pd = pd + pl->p_off[b];
-        st = run_wavefront(dc, pl->ci[b], m_all + pl->tab_off[b], s_all + pl->tab_off[b], stream);
-    }
+    if (st == MCM_OK && pl->has_wide && pl->wide.tables)
+        st = exec_tiled_plan(pl->wide.tp, (const TileChain *)pl->wide.tables,
+                             (const TileSeg *)((const char *)pl->wide.tables + pl->wide.seg_off),
+                             p_dev, pd, m_all, s_all, nullptr, stream);
     ws_free(pd, stream);
     ws_free(dims, stream);
     return st;

@@ -247,7 +247,8 @@ mcm_status run_pipeline_solve(const int32_t *p_dev, int32_t n, int64_t *m, int32
 mcm_status run_wavefront(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int32_t *s,
                          hipStream_t stream);
 
-// Tiled path (exact integers carried in fp64; see tiled_accepts).
+// Tiled path.  tiled_accepts: the chain fits the fp64-key kernels (exact
+// integers carried in fp64); other chains run the int64 tiled kernels.
 bool tiled_accepts(const ChainInfo &ci);
 mcm_status run_tiled(const DeviceChain &dc, const ChainInfo &ci, int64_t *m, int32_t *s,
                      hipStream_t stream);
@@ -263,6 +264,8 @@ struct TiledPlan {
     size_t part_elems = 0;             // partial-minima buffer (uint64) the plan needs
     bool lone = false;                 // one chain: fit bulk chunks to the GPU's slots
     bool serial = false;               // lone: one stream, chunks fitted to the whole device
+    bool wide = false;                 // exact int64 kernels (chains beyond the fp64
+                                       // keys' range); 64-edge tiles, no weights
     int chunk_target = 0;              // > 0: about this many interior chunks per
                                        // tile-diagonal (bulk_layout_chunks), device-independent
     int cus = 0;                       // lone: compute units of the device

@@ -15,6 +15,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
 #include <random>
 #include <set>
@@ -129,7 +130,7 @@ static void check_plan(const TiledPlan &plan, int T, const char *what)
     // partial regions read by the closures of D and written by the bulks of
     // D+1, per D (one lockstep iteration)
     std::map<int, std::vector<std::pair<int64_t, int64_t>>> reads, writes;
-    const int64_t TT = (int64_t)T * T;
+    const int64_t TT = (int64_t)T * T * (plan.wide ? 2 : 1);  // partial words per slot
     for (size_t li = 0; li < plan.launches.size(); ++li) {
         const TiledLaunch &L = plan.launches[li];
         int blocks = 0;
@@ -205,6 +206,116 @@ static void check_plan(const TiledPlan &plan, int T, const char *what)
     if (g_fail != fail0) fprintf(stderr, "  in plan: %s\n", what);
 }
 
+// Static race check of a plan's schedule.  Launches run on two streams (the
+// caller's, 0, and the library's second, 1) in plan order per stream, and a
+// launch that names another stream's launch in `wait` starts after it
+// (event or signal token).  Vector clocks give, for every launch, the last
+// launch of each stream that has finished before it starts.  Every read of
+// a table tile or a partial slot must then follow the launch that wrote it,
+// and every write must follow the earlier reads and writes of the same
+// resource (no write-after-read or write-after-write race): the readiness
+// that a debug build would assert at run time, proven for the whole plan.
+static void check_schedule(const TiledPlan &plan, int T, const char *what)
+{
+    const int fail0 = g_fail;
+    const size_t nl = plan.launches.size();
+    std::vector<int> stream(nl), pos(nl);
+    std::vector<std::array<int, 2>> vc(nl);
+    int count[2] = {0, 0};
+    std::array<int, 2> last_vc[2] = {{-1, -1}, {-1, -1}};
+    for (size_t li = 0; li < nl; ++li) {
+        const TiledLaunch &L = plan.launches[li];
+        const int st = L.stream;
+        stream[li] = st;
+        pos[li] = count[st]++;
+        std::array<int, 2> v = last_vc[st];
+        v[st] = pos[li];
+        if (L.wait >= 0) {
+            CHECK(L.wait < (int)li);
+            const std::array<int, 2> &w = vc[(size_t)L.wait];
+            v[0] = std::max(v[0], w[0]);
+            v[1] = std::max(v[1], w[1]);
+        }
+        vc[li] = v;
+        last_vc[st] = v;
+    }
+    // W finishes before L starts.
+    auto before = [&](int W, int L) {
+        return W != L && pos[(size_t)W] <= vc[(size_t)L][stream[(size_t)W]] &&
+               (stream[(size_t)W] != stream[(size_t)L] || W < L);
+    };
+    // Resources: tiles (chain, I, J) and partial slots (start element).
+    struct Use {
+        int writer = -1;
+        std::vector<int> readers;
+    };
+    std::map<std::tuple<int, int, int>, Use> tiles;
+    std::map<int64_t, Use> slots;
+    const int64_t words = plan.wide ? 2 : 1;
+    const int64_t TT = (int64_t)T * T * words;
+    auto read = [&](Use &u, int L, const char *kind) {
+        if (u.writer < 0 || !before(u.writer, L)) {
+            fprintf(stderr, "  %s read by launch %d not ordered after its writer %d\n", kind, L,
+                    u.writer);
+            CHECK(false);
+        }
+        u.readers.push_back(L);
+    };
+    auto write = [&](Use &u, int L, const char *kind) {
+        if (u.writer >= 0 && u.writer != L && !before(u.writer, L)) {
+            fprintf(stderr, "  %s written by launch %d races its writer %d\n", kind, L,
+                    u.writer);
+            CHECK(false);
+        }
+        for (int R : u.readers)
+            if (R != L && !before(R, L)) {
+                fprintf(stderr, "  %s written by launch %d races its reader %d\n", kind, L, R);
+                CHECK(false);
+            }
+        u.writer = L;
+        u.readers.clear();
+    };
+    for (size_t li = 0; li < nl && g_fail == fail0; ++li) {
+        const TiledLaunch &L = plan.launches[li];
+        const int l = (int)li;
+        for (int u = 0; u < L.nseg; ++u) {
+            const TileSeg &sg = plan.segs[(size_t)L.seg_begin + u];
+            const int c = sg.chain, NT = plan.NT[c];
+            if (L.kind == TK_TRI) {
+                for (int I = 0; I < NT; ++I) write(tiles[{c, I, I}], l, "diagonal tile");
+                continue;
+            }
+            const int D = sg.D;
+            for (int I = 0; I + D < NT; ++I) {
+                const int J = I + D;
+                if (L.kind == TK_CLOSE) {
+                    read(tiles[{c, I, I}], l, "tile");
+                    read(tiles[{c, J, J}], l, "tile");
+                    if (D >= 2)
+                        for (int sl = 0; sl < sg.PT; ++sl)
+                            read(slots[sg.part_off + ((int64_t)I * sg.PT + sl) * TT], l,
+                                 "partial");
+                    write(tiles[{c, I, J}], l, "tile");
+                    continue;
+                }
+                const int n = plan.chains[c].n;
+                const int kbase = (I + 1) * T - 1 + sg.koff;
+                for (int ch = 0; ch < sg.nch; ++ch) {
+                    const int k0 = kbase + ch * sg.KS;
+                    const int k1 = std::min(k0 + sg.KS, kbase + sg.klen);  // exclusive
+                    CHECK(k0 < k1 && k1 <= n);
+                    for (int K = k0 / T; K <= (k1 - 1) / T; ++K) read(tiles[{c, I, K}], l, "tile");
+                    for (int K = (k0 + 1) / T; K <= k1 / T && K <= J; ++K)
+                        read(tiles[{c, K, J}], l, "tile");
+                    write(slots[sg.part_off + ((int64_t)I * sg.PT + sg.slot0 + ch) * TT], l,
+                          "partial");
+                }
+            }
+        }
+    }
+    if (g_fail != fail0) fprintf(stderr, "  in schedule: %s\n", what);
+}
+
 static void check_lone_plans()
 {
     const int ns[] = {1, 2, 31, 32, 33, 63, 64, 65, 128, 129, 191, 193, 300, 1000, 2048, 3001,
@@ -217,6 +328,7 @@ static void check_lone_plans()
             CHECK(chain_bound(n, 1024, &ci) == MCM_OK);
             TiledPlan plan;
             plan.T = T;
+            plan.wide = T == 64 && (n % 3) == 0;
             plan.lone = mode != 3;
             plan.serial = mode == 1;
             plan.chunk_target = mode == 2 ? 512 : 0;
@@ -228,6 +340,7 @@ static void check_lone_plans()
             char what[64];
             snprintf(what, sizeof what, "lone n=%d mode=%d T=%d", n, mode, T);
             check_plan(plan, T, what);
+            check_schedule(plan, T, what);
             size_t seg_off = 0;
             const size_t bytes = plan_tables_bytes(plan, &seg_off);
             std::vector<char> buf(bytes + 1, (char)0x5a);
@@ -244,6 +357,7 @@ static void check_batch_plans()
     for (int trial = 0; trial < 12; ++trial) {
         TiledPlan plan;
         plan.T = trial % 2 ? 32 : 64;
+        plan.wide = trial == 4 || trial == 8;
         std::vector<int> ids;
         const int count = trial >= 10 ? 4096 : 1 + (int)(rng() % 300);
         int64_t off = 0;
@@ -256,8 +370,10 @@ static void check_batch_plans()
         }
         plan_lockstep(plan, ids);
         char what[64];
-        snprintf(what, sizeof what, "batch trial %d count %d T %d", trial, count, plan.T);
+        snprintf(what, sizeof what, "batch trial %d count %d T %d wide %d", trial, count,
+                 plan.T, (int)plan.wide);
         check_plan(plan, plan.T, what);
+        check_schedule(plan, plan.T, what);
     }
 }
 

@@ -56,8 +56,8 @@ def test_check_chain(lib):
 def test_select_algo(lib):
     assert binding.select_algo(workloads.single_n8192()) == binding.ALGO_TILED
     assert binding.select_algo(workloads.single_n128()) == binding.ALGO_TILED
-    # (n-1) * pmax^3 >= 2^46 leaves too few fp64 bits: int64 wavefront.
-    assert binding.select_algo([1 << 16] * 5) == binding.ALGO_WAVEFRONT
+    # (n-1) * pmax^3 >= 2^46 leaves too few fp64 bits: the int64 tiled kernels.
+    assert binding.select_algo([1 << 16] * 5) == binding.ALGO_TILED
     assert binding.select_algo([0, 1]) == -binding.ERR_INVALID_ARG
     assert binding.select_algo([1 << 21] * 3) == -binding.ERR_OVERFLOW
 
@@ -83,8 +83,8 @@ def test_solve_rejects_bad_input_before_device(lib):
     assert _solve_raw(lib, [2, 3, 4], mp + 4, sp) == binding.ERR_INVALID_ARG   # misaligned
     assert _solve_raw(lib, [2, 3, 4], mp, sp + 2) == binding.ERR_INVALID_ARG
     assert _solve_raw(lib, [2, 3, 4], mp, sp, algo=9) == binding.ERR_INVALID_ARG
-    assert _solve_raw(lib, [1 << 16] * 5, mp, sp, algo=binding.ALGO_TILED) == \
-        binding.ERR_UNSUPPORTED
+    assert _solve_raw(lib, [2] * 1100, mp, sp, algo=binding.ALGO_PIPELINE) == \
+        binding.ERR_UNSUPPORTED                                                # n > 1025
     assert np.all(m == 7) and np.all(s == 7)
 
 

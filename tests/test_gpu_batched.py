@@ -55,7 +55,7 @@ def test_mixed_sizes_and_paths():
     for t in range(40):
         n = int(rng.integers(1, 330))
         chains.append(workloads.uniform_dims(n, 1, 1024, 100 + t))
-    # Outside the fp64-exact range: takes the int64 wavefront inside the batch.
+    # Outside the fp64 keys' range: the int64 tiled kernels inside the batch.
     chains.append(workloads.uniform_dims(20, (1 << 19) - 9, 1 << 19, 5))
     chains += [workloads.all_equal(130, 7), workloads.tie_heavy(200, 3), np.array([5, 6])]
     batch = workloads.make_batch(chains)
@@ -131,13 +131,13 @@ def test_plan_reused_for_new_dims():
 
 
 def test_plan_wavefront_chains():
-    # A dims bound outside the fp64-exact range sends every chain of the
-    # plan to the int64 wavefront.
+    # A dims bound outside the fp64 keys' exact range sends every chain of
+    # the plan to the int64 tiled kernels.
     chains = [workloads.uniform_dims(n, (1 << 19) - 9, 1 << 19, 30 + n) for n in (1, 2, 7, 20)]
     batch = workloads.make_batch(chains)
     off = binding.table_offsets(batch.ns)
     total = int(off[-1] + int(batch.ns[-1]) ** 2)
-    _say("[gpu] plan wavefront max_dim=2^19")
+    _say("[gpu] plan int64 tiles max_dim=2^19")
     with binding.Plan(batch.ns, batch.p_off, off, 1 << 19) as plan:
         m_all, s_all, _ = _plan_solve(plan, batch.p_all, total)
     check_against_oracle(batch, off, m_all, s_all)
@@ -180,8 +180,8 @@ def test_plan_empty_and_mixed_paths():
         plan.solve_into(np.array([1], dtype=np.int32), m, s)
     torch.cuda.synchronize()
     assert int(m.abs().sum()) == 0 and int(s.abs().sum()) == 0
-    # A dims bound of 2^15 keeps n = 1, 2 in the fp64-exact tiled range and
-    # sends longer chains to the int64 wavefront: both paths in one plan.
+    # A dims bound of 2^15 keeps n = 1, 2 in the fp64 keys' range and sends
+    # longer chains to the int64 tiled kernels: both kinds in one plan.
     chains = [workloads.uniform_dims(n, 1, 1 << 15, 60 + n) for n in (2, 5, 1, 40, 2, 130)]
     batch = workloads.make_batch(chains)
     off = binding.table_offsets(batch.ns)

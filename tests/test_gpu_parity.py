@@ -96,14 +96,13 @@ def test_config_n2048(algo):
     assert_tables_equal(workloads.single_n2048(), algo)
 
 
-def test_wavefront_large_values():
-    # Costs near 2^62: beyond the fp64-exact range of the tiled path.
+@pytest.mark.parametrize("algo", ["wavefront", "tiled", "auto"])
+def test_large_values(algo):
+    # Costs near 2^62: beyond the fp64 keys' exact range; the tiled path
+    # runs its int64 kernels, the wavefront its int64 lanes.
     p = workloads.uniform_dims(32, (1 << 19) - 50, 1 << 19, 5)
-    assert binding.select_algo(p) == binding.ALGO_WAVEFRONT
-    assert_tables_equal(p, "auto")
-    with pytest.raises(binding.MCMError) as ei:
-        binding.solve(p, algo="tiled")
-    assert ei.value.status == binding.ERR_UNSUPPORTED
+    assert binding.select_algo(p) == binding.ALGO_TILED
+    assert_tables_equal(p, algo)
 
 
 def test_tiled_at_its_range_limit():
