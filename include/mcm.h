@@ -212,6 +212,23 @@ mcm_status mcm_solve_batched(int32_t count, const int32_t *n, const int64_t *p_o
  *                     order: up to `cap` entries of tile edge, threshold (0:
  *                     the CU count) and the last autotune's time in ms (-1
  *                     if never timed); *count receives the full number.
+ *   mcm_plan_graph_create  records the plan's whole solve -- the widening of
+ *                     the dims and every launch of every tile-diagonal on both
+ *                     streams, in the configuration in use at the call --
+ *                     into a HIP graph by stream capture on `stream` (not the
+ *                     null stream), for the fixed outputs m_all / s_all
+ *                     (device, as in mcm_plan_solve).  The plan then owns the
+ *                     graph, a second stream for it and the device buffers
+ *                     it reads (dims, their fp64 copies, partial minima); an
+ *                     earlier graph of the plan is released.  Cross-stream
+ *                     edges are events.  Nothing runs on the device.
+ *   mcm_plan_graph_solve  one solve by replay: copies p_all (host, checked
+ *                     against max_dim as in mcm_plan_solve) to the plan's
+ *                     dims buffer on `stream` and launches the graph there;
+ *                     the tables land in the m_all / s_all the graph was
+ *                     recorded for.  MCM_ERR_INVALID_ARG without a graph.
+ *                     Replays of one plan must be ordered on one stream (they
+ *                     share its buffers).
  *   mcm_plan_destroy  frees the plan (its device tables with hipFree, so
  *                     after the device has finished with them); NULL is
  *                     ignored.
@@ -229,6 +246,9 @@ mcm_status mcm_plan_config(const mcm_plan *plan, int32_t *tile_edge, int32_t *pa
 mcm_status mcm_plan_set_config(mcm_plan *plan, int32_t tile_edge, int32_t pair_min_blocks);
 mcm_status mcm_plan_candidates(const mcm_plan *plan, int32_t cap, int32_t *tile_edge,
                                int32_t *pair_min_blocks, float *ms, int32_t *count);
+mcm_status mcm_plan_graph_create(mcm_plan *plan, int64_t *m_all, int32_t *s_all,
+                                 hipStream_t stream);
+mcm_status mcm_plan_graph_solve(const mcm_plan *plan, const int32_t *p_all, hipStream_t stream);
 void mcm_plan_destroy(mcm_plan *plan);
 
 /*

@@ -38,7 +38,7 @@ EXPORTED = (
     "mcm_status_string", "mcm_version", "mcm_check_chain", "mcm_select_algo",
     "mcm_solve", "mcm_solve_algo", "mcm_solve_batched", "mcm_plan_create", "mcm_plan_solve",
     "mcm_plan_autotune", "mcm_plan_config", "mcm_plan_set_config", "mcm_plan_candidates",
-    "mcm_plan_destroy", "mcm_chain_create", "mcm_chain_solve", "mcm_chain_n",
+    "mcm_plan_graph_create", "mcm_plan_graph_solve", "mcm_plan_destroy", "mcm_chain_create", "mcm_chain_solve", "mcm_chain_n",
     "mcm_chain_destroy", "mcm_server_create", "mcm_server_submit", "mcm_server_poll",
     "mcm_server_release", "mcm_server_request_bytes", "mcm_server_stats", "mcm_server_destroy", "mcm_clock_now",
     "mcm_profile_enable", "mcm_profile_enable_mask", "mcm_profile_read", "mcm_parens_length", "mcm_parenthesize",
@@ -125,6 +125,10 @@ def load() -> ctypes.CDLL:
                                                 ctypes.POINTER(ctypes.c_float),
                                                 ctypes.POINTER(ctypes.c_int32)]
             lib.mcm_plan_candidates.restype = ctypes.c_int
+            lib.mcm_plan_graph_create.argtypes = [vp, vp, vp, vp]
+            lib.mcm_plan_graph_create.restype = ctypes.c_int
+            lib.mcm_plan_graph_solve.argtypes = [vp, i32p, vp]
+            lib.mcm_plan_graph_solve.restype = ctypes.c_int
             lib.mcm_plan_destroy.argtypes = [vp]
             lib.mcm_plan_destroy.restype = None
             lib.mcm_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, vp,
@@ -526,6 +530,28 @@ class Plan:
         if st != OK:
             raise MCMError(st, "mcm_plan_autotune")
         return int(choice.value)
+
+    def graph_create(self, m_all, s_all, stream=None) -> None:
+        """Record the plan's solve into a HIP graph for these outputs."""
+        import torch
+        self._args(np.ones(self.p_len, dtype=np.int32), m_all, s_all)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        st = load().mcm_plan_graph_create(self._h, ctypes.c_void_p(m_all.data_ptr()),
+                                          ctypes.c_void_p(s_all.data_ptr()),
+                                          ctypes.c_void_p(_stream_handle(stream)))
+        if st != OK:
+            raise MCMError(st, "mcm_plan_graph_create")
+
+    def graph_solve(self, p_all, stream=None) -> None:
+        """One solve by replaying the recorded graph with new dims."""
+        p_all = np.ascontiguousarray(np.asarray(p_all, dtype=np.int32))
+        if p_all.size < self.p_len:
+            raise ValueError("p_all too short for the plan's offsets")
+        st = load().mcm_plan_graph_solve(self._h, _p_ptr(p_all),
+                                         ctypes.c_void_p(_stream_handle(stream)))
+        if st != OK:
+            raise MCMError(st, "mcm_plan_graph_solve")
 
     def config(self) -> dict:
         """{'tile_edge', 'pair_min_blocks', 'source'} of the configuration in use."""

@@ -1597,7 +1597,7 @@ mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double 
 mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const TileSeg *segs,
                            const int32_t *p, const double *pd, int64_t *m_all, int32_t *s_all,
                            uint64_t *part_ext, hipStream_t stream, const ObstWeights *ob,
-                           int pair_min_blocks)
+                           int pair_min_blocks, hipStream_t aux_stream, bool events_only)
 {
     if (plan.launches.empty()) return MCM_OK;
     mcm_status st = MCM_OK;
@@ -1615,6 +1615,8 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
     // Events: one per launch another launch waits for, plus fork and join.
     StreamSet ss;
     if (aux && acquire_streams(nrec + 2, &ss) != MCM_OK) st = MCM_ERR_DEVICE;
+    hipStream_t lib_aux = ss.aux;
+    if (aux && aux_stream) ss.aux = aux_stream;
     std::vector<hipEvent_t> rec(plan.launches.size(), nullptr);
     // Aux launches the caller's stream waits for hand over a signal token
     // instead of an event when the device has a signal word (a stream wait
@@ -1708,7 +1710,7 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
             e = hipGetLastError();
         }
         if (e == hipSuccess && L.record && aux) {
-            if (L.stream == 1) tok[li] = aux_signal_write(ss.aux);
+            if (L.stream == 1 && !events_only && !aux_stream) tok[li] = aux_signal_write(ss.aux);
             if (!tok[li]) {
                 rec[li] = ss.events[next_ev++];
                 e = hipEventRecord(rec[li], q);
@@ -1722,6 +1724,7 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
             hipStreamWaitEvent(stream, ss.events[1], 0) != hipSuccess)
             st = MCM_ERR_DEVICE;
     }
+    ss.aux = lib_aux;
     if (aux) release_streams(ss);
     if (part_own) ws_free(part_own, stream);
     return st;

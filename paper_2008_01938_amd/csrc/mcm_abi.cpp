@@ -392,6 +392,10 @@ ProfileScope::ProfileScope(int cls, hipStream_t stream, double evals)
     : cls_(cls), stream_(stream), evals_(evals)
 {
     if (!((g_prof_mask.load(std::memory_order_relaxed) >> cls) & 1u)) return;
+    // Launches recorded into a graph are not timed.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return;
     start_ = prof_event_take();
     if (start_ && hipEventRecord(start_, stream_) != hipSuccess) {
         std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -551,11 +555,34 @@ struct mcm_plan {
     std::string key;                // tuning-cache bucket
     std::vector<PlanConfig> cands;  // configurations the plan can run
     std::vector<float> cand_ms;     // their times in the last autotune (-1: not timed)
-    ~mcm_plan()
+    // Graph form (mcm_plan_graph_create): the captured schedule and the
+    // device buffers it reads: dims, their fp64 copies, partial minima.
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t gaux = nullptr;     // the captured schedule's second stream
+    void *gmem = nullptr;
+    int32_t *g_dims = nullptr;
+    ~mcm_plan() { release(); }
+    void release_graph()
     {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (gmem) (void)hipFree(gmem);
+        if (gaux) (void)hipStreamDestroy(gaux);
+        gexec = nullptr;
+        graph = nullptr;
+        gmem = nullptr;
+        gaux = nullptr;
+        g_dims = nullptr;
+    }
+    void release()
+    {
+        release_graph();
         for (PlanVariant &v : var)
             if (v.tables) (void)hipFree(v.tables);
         if (wide.tables) (void)hipFree(wide.tables);
+        for (PlanVariant &v : var) v.tables = nullptr;
+        wide.tables = nullptr;
     }
 };
 
@@ -762,15 +789,10 @@ mcm_status mcm_plan_create(int32_t count, const int32_t *n, const int64_t *p_off
 
 namespace {
 
-mcm_status plan_solve(const mcm_plan *pl, const int32_t *p_all, int64_t *m_all, int32_t *s_all,
-                      hipStream_t stream, const PlanConfig &cfg)
+// Every dimension a chain of the plan reads must lie in [1, max_dim]: the
+// plan's key widths were sized for that bound.
+bool plan_dims_ok(const mcm_plan *pl, const int32_t *p_all)
 {
-    if (pl == nullptr || p_all == nullptr) return MCM_ERR_INVALID_ARG;
-    if (pl->count == 0) return MCM_OK;
-    if (!m_all || !s_all) return MCM_ERR_INVALID_ARG;
-    if (((uintptr_t)m_all & 7) != 0 || ((uintptr_t)s_all & 3) != 0) return MCM_ERR_INVALID_ARG;
-    // Every dimension a chain reads must lie in [1, max_dim]: the plan's key
-    // widths were sized for that bound.
     for (int32_t b = 0; b < pl->count; ++b) {
         const int32_t *p = p_all + pl->p_off[b];
         int32_t lo = INT32_MAX, hi = 0;
@@ -778,8 +800,19 @@ mcm_status plan_solve(const mcm_plan *pl, const int32_t *p_all, int64_t *m_all, 
             lo = p[t] < lo ? p[t] : lo;
             hi = p[t] > hi ? p[t] : hi;
         }
-        if (lo < 1 || hi > pl->max_dim) return MCM_ERR_INVALID_ARG;
+        if (lo < 1 || hi > pl->max_dim) return false;
     }
+    return true;
+}
+
+mcm_status plan_solve(const mcm_plan *pl, const int32_t *p_all, int64_t *m_all, int32_t *s_all,
+                      hipStream_t stream, const PlanConfig &cfg)
+{
+    if (pl == nullptr || p_all == nullptr) return MCM_ERR_INVALID_ARG;
+    if (pl->count == 0) return MCM_OK;
+    if (!m_all || !s_all) return MCM_ERR_INVALID_ARG;
+    if (((uintptr_t)m_all & 7) != 0 || ((uintptr_t)s_all & 3) != 0) return MCM_ERR_INVALID_ARG;
+    if (!plan_dims_ok(pl, p_all)) return MCM_ERR_INVALID_ARG;
     int dev = -1;
     if (hipGetLastError() != hipSuccess || hipGetDevice(&dev) != hipSuccess)
         return MCM_ERR_DEVICE;
@@ -908,6 +941,88 @@ mcm_status mcm_plan_candidates(const mcm_plan *plan, int32_t cap, int32_t *tile_
     }
     *count = (int32_t)plan->cands.size();
     return MCM_OK;
+}
+
+mcm_status mcm_plan_graph_create(mcm_plan *plan, int64_t *m_all, int32_t *s_all,
+                                 hipStream_t stream)
+{
+    if (plan == nullptr || !m_all || !s_all) return MCM_ERR_INVALID_ARG;
+    if (((uintptr_t)m_all & 7) != 0 || ((uintptr_t)s_all & 3) != 0) return MCM_ERR_INVALID_ARG;
+    if (stream == nullptr) return MCM_ERR_INVALID_ARG;  // the null stream cannot be captured
+    int dev = -1;
+    if (hipGetLastError() != hipSuccess || hipGetDevice(&dev) != hipSuccess)
+        return MCM_ERR_DEVICE;
+    if (dev != plan->device) return MCM_ERR_INVALID_ARG;
+    plan->release_graph();
+    const PlanVariant &pv = plan->var[plan->cfg.T == 32 && plan->has_var[1] ? 1 : 0];
+    // Device buffers the graph reads: dims, fp64 dims, partial minima of the
+    // configured schedule and of the int64 one.
+    const size_t np = (size_t)(plan->p_len > 0 ? plan->p_len : 1);
+    const size_t at_pd = (np * sizeof(int32_t) + 255) / 256 * 256;
+    const size_t at_part = at_pd + (np * sizeof(double) + 255) / 256 * 256;
+    const size_t part1 = (pv.tables ? pv.tp.part_elems : 0) * sizeof(uint64_t);
+    const size_t at_wide = at_part + (part1 + 255) / 256 * 256;
+    const size_t part2 = (plan->has_wide ? plan->wide.tp.part_elems : 0) * sizeof(uint64_t);
+    if (hipMalloc(&plan->gmem, at_wide + part2 + 256) != hipSuccess) {
+        plan->gmem = nullptr;
+        return MCM_ERR_NO_MEMORY;
+    }
+    if (hipStreamCreateWithFlags(&plan->gaux, hipStreamNonBlocking) != hipSuccess) {
+        plan->gaux = nullptr;
+        plan->release_graph();
+        return MCM_ERR_DEVICE;
+    }
+    char *base = (char *)plan->gmem;
+    plan->g_dims = (int32_t *)base;
+    double *pd = (double *)(base + at_pd);
+    // Warm the library's stream set (events) before capturing.
+    StreamSet warm;
+    if (acquire_streams(0, &warm) != MCM_OK) {
+        plan->release_graph();
+        return MCM_ERR_DEVICE;
+    }
+    release_streams(warm);
+    mcm_status st = MCM_OK;
+    if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        plan->release_graph();
+        return MCM_ERR_DEVICE;
+    }
+    st = widen_dims(plan->g_dims, pd, np, stream);
+    if (st == MCM_OK && pv.tables)
+        st = exec_tiled_plan(pv.tp, (const TileChain *)pv.tables,
+                             (const TileSeg *)((const char *)pv.tables + pv.seg_off),
+                             plan->g_dims, pd, m_all, s_all, (uint64_t *)(base + at_part), stream,
+                             nullptr, plan->cfg.pair_min, plan->gaux, true);
+    if (st == MCM_OK && plan->has_wide && plan->wide.tables)
+        st = exec_tiled_plan(plan->wide.tp, (const TileChain *)plan->wide.tables,
+                             (const TileSeg *)((const char *)plan->wide.tables +
+                                               plan->wide.seg_off),
+                             plan->g_dims, pd, m_all, s_all, (uint64_t *)(base + at_wide),
+                             stream, nullptr, -1, plan->gaux, true);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(stream, &g);
+    if (st == MCM_OK && (ec != hipSuccess || g == nullptr)) st = MCM_ERR_DEVICE;
+    plan->graph = g;
+    if (st == MCM_OK && hipGraphInstantiate(&plan->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+        plan->gexec = nullptr;
+        st = MCM_ERR_DEVICE;
+    }
+    if (st != MCM_OK) plan->release_graph();
+    return st;
+}
+
+mcm_status mcm_plan_graph_solve(const mcm_plan *plan, const int32_t *p_all, hipStream_t stream)
+{
+    if (plan == nullptr || p_all == nullptr || plan->gexec == nullptr) return MCM_ERR_INVALID_ARG;
+    if (!plan_dims_ok(plan, p_all)) return MCM_ERR_INVALID_ARG;
+    if (hipGetLastError() != hipSuccess) return MCM_ERR_DEVICE;
+    const size_t np = (size_t)plan->p_len;
+    if (np > 0) {
+        const mcm_status st = upload_to(stream, plan->g_dims, np * sizeof(int32_t),
+                                        [&](char *h) { memcpy(h, p_all, np * sizeof(int32_t)); });
+        if (st != MCM_OK) return st;
+    }
+    return hipGraphLaunch(plan->gexec, stream) == hipSuccess ? MCM_OK : MCM_ERR_DEVICE;
 }
 
 void mcm_plan_destroy(mcm_plan *plan)

@@ -331,9 +331,13 @@ size_t plan_tables_bytes(const TiledPlan &plan, size_t *seg_offset);
 void plan_tables_write(const TiledPlan &plan, char *dst);
 // run_tiled_plan with the plan's tables already on the device.
 // pair_min_blocks >= 0 overrides the plan's closure-shape threshold.
+// aux_stream: the second stream to use instead of the library's (whose
+// signal tokens are then not used either); events_only: cross-stream edges
+// as events only (what a stream capture records).
 mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const TileSeg *segs,
                            const int32_t *p, const double *pd, int64_t *m_all, int32_t *s_all,
                            uint64_t *part_ext, hipStream_t stream,
-                           const ObstWeights *ob = nullptr, int pair_min_blocks = -1);
+                           const ObstWeights *ob = nullptr, int pair_min_blocks = -1,
+                           hipStream_t aux_stream = nullptr, bool events_only = false);
 
 }  // namespace mcm

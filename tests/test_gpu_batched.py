@@ -271,3 +271,47 @@ def test_plan_configurations_and_autotune_record():
             assert cfg["source"] == "tuned" and cfg["tile_edge"] == cands[choice]["tile_edge"]
         check_against_oracle(batch, off, m_all, s_all)
     torch.cuda.synchronize()
+
+
+# --------------------------------------------------------------------------
+# Graph form of a plan: the whole solve recorded once, replayed per solve.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("edge", [64, 32, "int64"])
+def test_plan_graph_replays_match_eager(edge):
+    # Three replays with new dims each, the program's own eager solves and
+    # synchronizations between them; every replay equals the eager plan
+    # solve of the same dims (whole buffers) and the oracle.  "int64": a dims
+    # bound beyond the fp64 keys' range puts every chain on the int64
+    # schedule.
+    import torch
+    sizes = [1, 33, 64, 65, 150, 300, 513]
+    max_dim = 1024 if edge != "int64" else 1 << 17
+
+    def make(seed):
+        return workloads.make_batch([workloads.uniform_dims(n, max_dim // 4, max_dim,
+                                                            seed * 100 + n) for n in sizes])
+
+    first = make(1)
+    off = binding.table_offsets(first.ns)
+    total = int(off[-1] + int(first.ns[-1]) ** 2)
+    st = torch.cuda.Stream()
+    m_g = torch.full((total,), -9, dtype=torch.int64, device="cuda")
+    s_g = torch.full((total,), -9, dtype=torch.int32, device="cuda")
+    with binding.Plan(first.ns, first.p_off, off, max_dim) as plan:
+        if edge != "int64":
+            plan.set_config(edge)
+        _say(f"[gpu] plan graph capture, {edge}")
+        plan.graph_create(m_g, s_g, stream=st)
+        st.synchronize()
+        for seed in (1, 2, 3):
+            batch = make(seed)
+            assert np.array_equal(batch.p_off, first.p_off)
+            _say(f"[gpu] graph replay seed={seed}")
+            plan.graph_solve(batch.p_all, stream=st)
+            st.synchronize()
+            m_e, s_e, _ = _plan_solve(plan, batch.p_all, total)   # eager, default stream
+            torch.cuda.synchronize()
+            assert np.array_equal(m_g.cpu().numpy(), m_e), f"replay {seed}: m"
+            assert np.array_equal(s_g.cpu().numpy(), s_e), f"replay {seed}: s"
+            check_against_oracle(batch, off, m_e, s_e)
