@@ -99,27 +99,39 @@ def test_n8192_dims_4096_whole_table():
     check(p)
 
 
-def test_batched_and_plan_mix_wide_and_fp64_chains():
+def _mixed_batch(chains, mode, max_dim=None):
     import torch
-    chains = [workloads.uniform_dims(n, 1, 1024, 900 + n) for n in (1, 40, 130, 300)]
-    chains += [workloads.uniform_dims(n, pmax_for(n) // 2, pmax_for(n), 950 + n)
-               for n in (2, 64, 150, 260)]
     batch = workloads.make_batch(chains)
     off = binding.table_offsets(batch.ns)
     total = int(off[-1] + int(batch.ns[-1]) ** 2)
-    for mode in ("oneshot", "plan"):
-        m_all = torch.full((total,), -9, dtype=torch.int64, device="cuda")
-        s_all = torch.full((total,), -9, dtype=torch.int32, device="cuda")
-        _say(f"[gpu] mixed wide/fp64 batch, {mode}")
-        if mode == "oneshot":
-            binding.solve_batched_into(batch.ns, batch.p_off, batch.p_all, off, m_all, s_all)
-        else:
-            with binding.Plan(batch.ns, batch.p_off, off, int(batch.p_all.max())) as plan:
-                plan.solve_into(batch.p_all, m_all, s_all)
-        torch.cuda.synchronize()
-        mh, sh = m_all.cpu().numpy(), s_all.cpu().numpy()
-        for b in range(batch.ns.size):
-            n, o = int(batch.ns[b]), int(off[b])
-            om, os_ = oracle.fill(batch.dims(b))
-            assert np.array_equal(mh[o:o + n * n].reshape(n, n), om), f"{mode} chain {b}"
-            assert np.array_equal(sh[o:o + n * n].reshape(n, n), os_), f"{mode} chain {b}"
+    m_all = torch.full((total,), -9, dtype=torch.int64, device="cuda")
+    s_all = torch.full((total,), -9, dtype=torch.int32, device="cuda")
+    _say(f"[gpu] mixed wide/fp64 batch, {mode}, ns={list(batch.ns)}")
+    if mode == "oneshot":
+        binding.solve_batched_into(batch.ns, batch.p_off, batch.p_all, off, m_all, s_all)
+    else:
+        with binding.Plan(batch.ns, batch.p_off, off, max_dim) as plan:
+            plan.solve_into(batch.p_all, m_all, s_all)
+    torch.cuda.synchronize()
+    mh, sh = m_all.cpu().numpy(), s_all.cpu().numpy()
+    for b in range(batch.ns.size):
+        n, o = int(batch.ns[b]), int(off[b])
+        om, os_ = oracle.fill(batch.dims(b))
+        assert np.array_equal(mh[o:o + n * n].reshape(n, n), om), f"{mode} chain {b}"
+        assert np.array_equal(sh[o:o + n * n].reshape(n, n), os_), f"{mode} chain {b}"
+
+
+def test_batched_and_plan_mix_wide_and_fp64_chains():
+    # One-shot: each chain's own dims decide its kernels.
+    chains = [workloads.uniform_dims(n, 1, 1024, 900 + n) for n in (1, 40, 130, 300)]
+    chains += [workloads.uniform_dims(n, pmax_for(n) // 2, pmax_for(n), 950 + n)
+               for n in (2, 64, 150, 260)]
+    _mixed_batch(chains, "oneshot")
+    # Plan: one bound on the dims for every chain, 2^14, so chains with
+    # (n-1) 2^42 < 2^46 (n <= 16) take the fp64 keys and the rest the int64
+    # kernels.
+    dmax = 1 << 14
+    chains = [workloads.uniform_dims(n, 1, dmax, 960 + n) for n in (1, 5, 12, 16)]
+    chains += [workloads.uniform_dims(n, dmax // 2, dmax, 970 + n)
+               for n in (17, 64, 130, 260, 300)]
+    _mixed_batch(chains, "plan", max_dim=dmax)
