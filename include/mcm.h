@@ -129,6 +129,30 @@ mcm_status mcm_solve_algo(const int32_t *p, int32_t n, int64_t *m_out, int32_t *
                           int32_t algo, hipStream_t stream);
 
 /*
+ * mcm_solve for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * call allocates nothing (no hipMalloc / hipFree / pinned host memory, no
+ * second stream or events): every buffer beyond p, m_out and s_out lives
+ * in one fixed device array of MCM_NOALLOC_SCRATCH_BYTES that the library
+ * holds on each device it runs on until the process ends.  Same arguments,
+ * output contract and validation as mcm_solve (MCM_ALGO_TILED, its
+ * schedule run on `stream` alone); the dims reach the device as kernel
+ * arguments, so p may be reused at once.
+ *   n > MCM_NOALLOC_MAX_N, or a chain whose tables and partial minima do
+ *   not fit the array (none up to that n), returns MCM_ERR_UNSUPPORTED
+ *   before anything is enqueued.
+ * Every call on one device shares that device's array, which keeps the
+ * last call's contents (nothing in it needs clearing: each call writes what
+ * it reads).  Calls that overlap on one device -- on different streams, or
+ * from different threads without ordering -- race on the array and must
+ * not be issued; calls ordered on one stream are safe.
+ */
+#define MCM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+#define MCM_NOALLOC_MAX_N 8192
+mcm_status mcm_solve_noalloc(const int32_t *p, int32_t n, int64_t *m_out, int32_t *s_out,
+                             hipStream_t stream);
+
+/*
  * Many independent chains in one call.  All chains advance together, one
  * tile-diagonal per iteration, each kernel launch serving every chain that
  * is still active, so a batch of thousands of small chains costs a few

@@ -36,15 +36,18 @@ PLAN_SOURCES = {0: "default", 1: "cache", 2: "tuned"}   # MCM_PLAN_*
 # Every symbol include/mcm.h declares.
 EXPORTED = (
     "mcm_status_string", "mcm_version", "mcm_check_chain", "mcm_select_algo",
-    "mcm_solve", "mcm_solve_algo", "mcm_solve_batched", "mcm_plan_create", "mcm_plan_solve",
-    "mcm_plan_autotune", "mcm_plan_config", "mcm_plan_set_config", "mcm_plan_candidates",
-    "mcm_plan_graph_create", "mcm_plan_graph_solve", "mcm_plan_destroy", "mcm_chain_create", "mcm_chain_solve", "mcm_chain_n",
-    "mcm_chain_destroy", "mcm_server_create", "mcm_server_submit", "mcm_server_poll",
-    "mcm_server_release", "mcm_server_request_bytes", "mcm_server_stats", "mcm_server_destroy", "mcm_clock_now",
-    "mcm_profile_enable", "mcm_profile_enable_mask", "mcm_profile_read", "mcm_parens_length", "mcm_parenthesize",
-    "mcm_parenthesize_batched", "mcm_sdp_solve", "mcm_obst_solve",
-    "mcm_obst_solve_algo",
+    "mcm_solve", "mcm_solve_algo", "mcm_solve_noalloc", "mcm_solve_batched",
+    "mcm_plan_create", "mcm_plan_solve", "mcm_plan_autotune", "mcm_plan_config",
+    "mcm_plan_set_config", "mcm_plan_candidates", "mcm_plan_graph_create",
+    "mcm_plan_graph_solve", "mcm_plan_destroy", "mcm_chain_create", "mcm_chain_solve",
+    "mcm_chain_n", "mcm_chain_destroy", "mcm_server_create", "mcm_server_submit",
+    "mcm_server_poll", "mcm_server_release", "mcm_server_request_bytes", "mcm_server_stats",
+    "mcm_server_destroy", "mcm_clock_now", "mcm_profile_enable", "mcm_profile_enable_mask",
+    "mcm_profile_read", "mcm_parens_length", "mcm_parenthesize", "mcm_parenthesize_batched",
+    "mcm_sdp_solve", "mcm_obst_solve", "mcm_obst_solve_algo",
 )
+NOALLOC_MAX_N = 8192             # MCM_NOALLOC_MAX_N
+NOALLOC_SCRATCH_BYTES = 64 << 20  # MCM_NOALLOC_SCRATCH_BYTES
 
 SDP_OPS = {"min": 0, "max": 1, "add": 2}
 
@@ -96,6 +99,8 @@ def load() -> ctypes.CDLL:
             lib.mcm_solve.restype = ctypes.c_int
             lib.mcm_solve_algo.argtypes = [i32p, ctypes.c_int32, vp, vp, ctypes.c_int32, vp]
             lib.mcm_solve_algo.restype = ctypes.c_int
+            lib.mcm_solve_noalloc.argtypes = [i32p, ctypes.c_int32, vp, vp, vp]
+            lib.mcm_solve_noalloc.restype = ctypes.c_int
             i64p = ctypes.POINTER(ctypes.c_int64)
             lib.mcm_solve_batched.argtypes = [ctypes.c_int32, i32p, i64p, i32p, i64p, vp, vp, vp]
             lib.mcm_solve_batched.restype = ctypes.c_int
@@ -234,6 +239,24 @@ def solve_into(p, m, s, algo: int | str = ALGO_AUTO, stream=None) -> None:
                                ctypes.c_void_p(_stream_handle(stream)))
     if st != OK:
         raise MCMError(st, "mcm_solve_algo")
+
+
+def solve_noalloc_into(p, m, s, stream=None) -> None:
+    """mcm_solve_noalloc: the solve of chain p into preallocated device
+    tensors (as solve_into) with no device allocation by the library; its
+    workspace is the library's fixed per-device array."""
+    import torch
+    a = _dims(p)
+    n = a.size - 1
+    if not (m.is_cuda and s.is_cuda and m.dtype == torch.int64 and s.dtype == torch.int32):
+        raise TypeError("m must be a CUDA int64 tensor and s a CUDA int32 tensor")
+    if not (m.is_contiguous() and s.is_contiguous()) or m.numel() < n * n or s.numel() < n * n:
+        raise ValueError("m and s must be contiguous with at least n*n elements")
+    st = load().mcm_solve_noalloc(_p_ptr(a), n, ctypes.c_void_p(m.data_ptr()),
+                                  ctypes.c_void_p(s.data_ptr()),
+                                  ctypes.c_void_p(_stream_handle(stream)))
+    if st != OK:
+        raise MCMError(st, "mcm_solve_noalloc")
 
 
 def solve(p, algo: int | str = ALGO_AUTO, device="cuda", stream=None):

@@ -340,4 +340,24 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
                            const ObstWeights *ob = nullptr, int pair_min_blocks = -1,
                            hipStream_t aux_stream = nullptr, bool events_only = false);
 
+// ------------------------------------------------------------------------
+// The no-allocation solve (mcm_noalloc.hip): scratch layout of one call, in
+// bytes from the fixed array's base (256-byte aligned regions).
+// ------------------------------------------------------------------------
+struct NoallocLayout {
+    size_t p_off = 0;      // int32 dims, n+1
+    size_t pd_off = 0;     // fp64 dims, n+1
+    size_t tab_off = 0;    // TileChain records, then TileSeg from tab_off + seg_rel
+    size_t seg_rel = 0;
+    size_t tab_bytes = 0;
+    size_t part_off = 0;   // packed partial minima, plan.part_elems uint64
+    size_t total = 0;      // bytes of the array the call uses
+};
+// The serial single-chain plan of the no-allocation solve and its layout:
+// bulk chunking fitted to the device (cus, slots_per_cu) if it fits in
+// `cap` bytes, else fewer chunks per tile-diagonal until it does.  False if
+// even one chunk per tile does not fit.  Host only.
+bool noalloc_plan(const ChainInfo &ci, int cus, int slots_per_cu, size_t cap, TiledPlan &plan,
+                  NoallocLayout &lay);
+
 }  // namespace mcm

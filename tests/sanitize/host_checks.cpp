@@ -377,12 +377,48 @@ static void check_batch_plans()
     }
 }
 
+// The no-allocation solve: for chains up to MCM_NOALLOC_MAX_N, with keys
+// (dims <= 1024) and on the int64 kernels (dims 2^16), a plan is found whose
+// dims, tables and partials fit the fixed array in disjoint aligned regions,
+// and it passes the same coverage and schedule checks.
+static void check_noalloc_plans()
+{
+    std::vector<int> ns = {1, 2, 3, 63, 64, 65, 127, 128, 129, 1000, 4095, 4096, 4097,
+                           8000, MCM_NOALLOC_MAX_N - 1, MCM_NOALLOC_MAX_N};
+    for (int n = 5; n < MCM_NOALLOC_MAX_N; n += 397) ns.push_back(n);
+    for (int n : ns)
+    for (int32_t pmax : {1024, 1 << 16}) {
+        ChainInfo ci;
+        CHECK(chain_bound(n, pmax, &ci) == MCM_OK);
+        for (int slots : {3, 0}) {
+            TiledPlan plan;
+            NoallocLayout lay;
+            const bool ok = noalloc_plan(ci, 256, slots, MCM_NOALLOC_SCRATCH_BYTES, plan, lay);
+            CHECK(ok);
+            if (!ok) continue;
+            CHECK(plan.wide == (pmax > 1024 && n > 1));
+            CHECK(!plan.uses_aux);
+            CHECK(lay.total <= MCM_NOALLOC_SCRATCH_BYTES);
+            CHECK(lay.pd_off >= (size_t)(n + 1) * 4 && lay.pd_off % 256 == 0);
+            CHECK(lay.tab_off >= lay.pd_off + (size_t)(n + 1) * 8 && lay.tab_off % 256 == 0);
+            CHECK(lay.part_off >= lay.tab_off + lay.tab_bytes && lay.part_off % 256 == 0);
+            CHECK(lay.total == lay.part_off + plan.part_elems * sizeof(uint64_t));
+            if (n % 397 == 5 && n > 2000) continue;  // coverage on a subset (time)
+            char what[64];
+            snprintf(what, sizeof what, "noalloc n=%d pmax=%d slots=%d", n, (int)pmax, slots);
+            check_plan(plan, 64, what);
+            check_schedule(plan, 64, what);
+        }
+    }
+}
+
 int main()
 {
     check_rejections();
     check_ranges();
     check_lone_plans();
     check_batch_plans();
+    check_noalloc_plans();
     if (g_fail) {
         fprintf(stderr, "%d checks failed\n", g_fail);
         return 1;

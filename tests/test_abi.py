@@ -88,6 +88,36 @@ def test_solve_rejects_bad_input_before_device(lib):
     assert np.all(m == 7) and np.all(s == 7)
 
 
+def test_noalloc_rejects_bad_input_before_device(lib):
+    # As mcm_solve, plus the size limit of the fixed array; host buffers
+    # stand in for device pointers and are never touched.
+    m = np.full(16, 7, dtype=np.int64)
+    s = np.full(16, 7, dtype=np.int32)
+    mp, sp = ctypes.c_void_p(m.ctypes.data), ctypes.c_void_p(s.ctypes.data)
+
+    def call(p, mp=mp, sp=sp):
+        a = np.ascontiguousarray(np.asarray(p, dtype=np.int32))
+        return lib.mcm_solve_noalloc(a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     a.size - 1, mp, sp, ctypes.c_void_p(0))
+
+    assert call([3]) == binding.ERR_INVALID_ARG
+    assert call([3, 0, 2]) == binding.ERR_INVALID_ARG
+    assert call([1 << 21] * 3) == binding.ERR_OVERFLOW
+    assert call([2, 3, 4], mp=ctypes.c_void_p(0)) == binding.ERR_INVALID_ARG
+    assert call([2, 3, 4], sp=ctypes.c_void_p(s.ctypes.data + 2)) == binding.ERR_INVALID_ARG
+    assert call(np.ones(binding.NOALLOC_MAX_N + 2, dtype=np.int32)) == binding.ERR_UNSUPPORTED
+    assert lib.mcm_solve_noalloc(None, 4, mp, sp, ctypes.c_void_p(0)) == binding.ERR_INVALID_ARG
+    assert np.all(m == 7) and np.all(s == 7)
+
+
+def test_noalloc_constants_match_header():
+    text = open(HEADER).read()
+    assert re.search(r"#define MCM_NOALLOC_MAX_N (\d+)", text).group(1) == \
+        str(binding.NOALLOC_MAX_N)
+    assert "#define MCM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)" in text
+    assert binding.NOALLOC_SCRATCH_BYTES == 64 << 20
+
+
 def test_profile_read_rejects_bad_class(lib):
     d = ctypes.c_double()
     n = ctypes.c_int64()
