@@ -350,14 +350,21 @@ __global__ __launch_bounds__(bulk_threads<T>()) void k_bulk(const TileChain *__r
     const double inv_scale = ldexp(1.0, -kb);
     const int tx = tid % TW, ty = tid / TW;
 
+    // The eight dims are loaded together (column indices clamped into the
+    // table, the products past the last column then zeroed) so that the
+    // prologue waits for memory once, not once per conditional load.
+    double pi4[4], pc4[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) pi4[a] = pd[row0 + ty + TW * a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) pc4[b] = pd[col0 + min(tx + TW * b, nJ - 1) + 1];
     double pj[4][4], best[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        const double pi = pd[row0 + ty + TW * a] * scale;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int c = tx + TW * b;
-            pj[a][b] = c < nJ ? pi * pd[col0 + c + 1] : 0.0;
+            const double v = pi4[a] * scale * pc4[b];
+            pj[a][b] = tx + TW * b < nJ ? v : 0.0;
             best[a][b] = __builtin_inf();
         }
     }
@@ -514,11 +521,12 @@ __device__ __forceinline__ double range_min(const double *v)
 }
 
 // One step of a row group: the minimum over its (a) and (b) splits of cell
-// (r, cc).  T0: the first (a) slot any row of the wave uses; TB: the (b)
-// slots any row of the wave can use (c' < c for its largest c).  A (b) slot
-// inside that bound whose cell is not final yet still holds Xrow = 2^62, so
-// whatever DJ value it meets, its term loses.
-template <int T, int G, int T0, int TB, class Lds>
+// (r, cc).  T0: the first (a) slot any row of the wave uses.  A (b) slot
+// whose cell is not final yet still holds Xrow = 2^62, so whatever DJ value
+// it meets, its term loses.  (Bounding the (b) slots per wave as well, by
+// instantiating the step per bound, measured slower: the larger code costs
+// more than the skipped slots save.)
+template <int T, int G, int T0, class Lds>
 __device__ __forceinline__ double close_step(const CloseRegs<T, G> &R, const Lds &L, int xo,
                                              int djb, int g, double pJc)
 {
@@ -528,40 +536,25 @@ __device__ __forceinline__ double close_step(const CloseRegs<T, G> &R, const Lds
 #pragma unroll
     for (int t = T0; t < CS; ++t) xa[t] = xcol[t * G + g + 1];
 #pragma unroll
-    for (int t = 0; t < TB; ++t) xb[t] = L.dj_at_base(djb, t * G + g);
+    for (int t = 0; t < CS; ++t) xb[t] = L.dj_at_base(djb, t * G + g);
     // Independent terms, then balanced min trees.
 #pragma unroll
     for (int t = T0; t < CS; ++t) va[t] = fma(pJc, R.PIr[t], R.DIr[t]) + xa[t];
 #pragma unroll
-    for (int t = 0; t < TB; ++t) vb[t] = fma(pJc, R.PJr[t], xb[t]) + R.Xrow[t];
-    double v;
-    if constexpr (TB == 0)
-        v = range_min<T0, CS>(va);
-    else
-        v = fmin(range_min<T0, CS>(va), range_min<0, TB>(vb));
-    return min_group<G>(v);
+    for (int t = 0; t < CS; ++t) vb[t] = fma(pJc, R.PJr[t], xb[t]) + R.Xrow[t];
+    return min_group<G>(fmin(range_min<T0, CS>(va), range_min<0, CS>(vb)));
 }
 
-// close_step with its slot bounds t0 and tb (wave-uniform) as template
-// arguments.
-template <int T, int G, int T0, int TB, class Lds>
-__device__ __forceinline__ double close_step_tb(int tb, const CloseRegs<T, G> &R, const Lds &L,
+// close_step with its first (a) slot t0 (wave-uniform) as a template
+// argument.
+template <int T, int G, int T0, class Lds>
+__device__ __forceinline__ double close_step_at(int t0, const CloseRegs<T, G> &R, const Lds &L,
                                                 int xo, int djb, int g, double pJc)
 {
-    if constexpr (TB + 1 <= CloseShape<T, G>::CS) {
-        if (tb > TB) return close_step_tb<T, G, T0, TB + 1>(tb, R, L, xo, djb, g, pJc);
-    }
-    return close_step<T, G, T0, TB>(R, L, xo, djb, g, pJc);
-}
-
-template <int T, int G, int T0, class Lds>
-__device__ __forceinline__ double close_step_at(int t0, int tb, const CloseRegs<T, G> &R,
-                                                const Lds &L, int xo, int djb, int g, double pJc)
-{
     if constexpr (T0 + 1 < CloseShape<T, G>::CS) {
-        if (t0 > T0) return close_step_at<T, G, T0 + 1>(t0, tb, R, L, xo, djb, g, pJc);
+        if (t0 > T0) return close_step_at<T, G, T0 + 1>(t0, R, L, xo, djb, g, pJc);
     }
-    return close_step_tb<T, G, T0, 0>(tb, R, L, xo, djb, g, pJc);
+    return close_step<T, G, T0>(R, L, xo, djb, g, pJc);
 }
 
 // OB: the optimal-BST weights (pd_all then holds zeros, so every product
@@ -598,16 +591,31 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
 
     const int r = tid / G, g = tid % G;
     const int h = __builtin_amdgcn_readfirstlane(tid / 64);  // rows CROWS*h ..
+    // Register operands.  Every load is issued unconditionally (indices
+    // clamped into the table) and the slots that do not apply are replaced
+    // afterwards, so the prologue -- on the solve's critical path -- waits
+    // for memory once instead of once per conditional load.
     CloseRegs<T, G> R;
     const double pi_s = pd[row0 + r] * scale;
+    {
+        double dm[CS], dpi[CS], dpj[CS];
 #pragma unroll
-    for (int t = 0; t < CS; ++t) {
-        const int q = t * G + g;  // (a) split column q; (b) split column c' = q
-        const bool qa = q >= r && q <= T - 2;
-        R.DIr[t] = qa ? fma((double)m[(size_t)(row0 + r) * n + row0 + q], scale, (double)q) : kPad;
-        R.PIr[t] = qa ? pi_s * pd[row0 + q + 1] : 0.0;
-        R.PJr[t] = q < nJ ? pi_s * pd[col0 + q + 1] : 0.0;
-        R.Xrow[t] = kPad;  // until cell (r, q) is final
+        for (int t = 0; t < CS; ++t) {
+            const int q = t * G + g;
+            const int qa = min(q, T - 2);
+            dm[t] = (double)m[(size_t)(row0 + r) * n + row0 + qa];
+            dpi[t] = pd[row0 + qa + 1];
+            dpj[t] = pd[col0 + min(q, nJ - 1) + 1];
+        }
+#pragma unroll
+        for (int t = 0; t < CS; ++t) {
+            const int q = t * G + g;  // (a) split column q; (b) split column c' = q
+            const bool qa = q >= r && q <= T - 2;
+            R.DIr[t] = qa ? fma(dm[t], scale, (double)q) : kPad;
+            R.PIr[t] = qa ? pi_s * dpi[t] : 0.0;
+            R.PJr[t] = q < nJ ? pi_s * dpj[t] : 0.0;
+            R.Xrow[t] = kPad;  // until cell (r, q) is final
+        }
     }
 
     if constexpr (OB) {
@@ -629,13 +637,24 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
         }
     }
     __syncthreads();
-    // DJ[q][c], 1 <= q <= c < nJ, read row-major (coalesced).
-#pragma unroll 4
-    for (int idx = tid; idx < T * T; idx += CTH) {
-        const int qq = idx / T, c = idx % T;
-        if (qq >= 1 && qq <= c && c < nJ)
-            L.dj(qq, c) = fma((double)m[(size_t)(col0 + qq) * n + col0 + c], scale,
-                              (double)(T + qq - 1));
+    // DJ[q][c], 1 <= q <= c < nJ, read row-major (coalesced); every
+    // thread's loads are issued together (indices clamped into the table)
+    // and only the entries that apply are stored.
+    {
+        constexpr int DPT = T * T / CTH;  // entries per thread
+        double dv[DPT];
+#pragma unroll
+        for (int u = 0; u < DPT; ++u) {
+            const int idx = tid + CTH * u;
+            const int qq = min(idx / T, nJ - 1), c = min(idx % T, nJ - 1);
+            dv[u] = (double)m[(size_t)(col0 + qq) * n + col0 + c];
+        }
+#pragma unroll
+        for (int u = 0; u < DPT; ++u) {
+            const int idx = tid + CTH * u;
+            const int qq = idx / T, c = idx % T;
+            if (qq >= 1 && qq <= c && c < nJ) L.dj(qq, c) = fma(dv[u], scale, (double)(T + qq - 1));
+        }
     }
     // Bulk result per cell: the minimum of the PT packed (cost << kbits | k)
     // partials, or for D == 1 the single bulk split k = (I+1)T-1 whose
@@ -659,28 +678,23 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
             }
         }
     } else {
+        // SPR slots' loads in flight per round trip (16 loads per thread); a
+        // last partial group re-reads its final slot, which changes no
+        // minimum.
+        constexpr int SPR = 16 / CPT;
         const uint64_t *src = part + ((size_t)I * PT) * T * T;
-        int sl = 0;
-        for (; sl + 2 <= PT; sl += 2) {
-            uint64_t v0[CPT], v1[CPT];
+        for (int sl = 0; sl < PT; sl += SPR) {
+            uint64_t v[SPR][CPT];
 #pragma unroll
-            for (int u = 0; u < CPT; ++u) {
-                const int idx = tid + CTH * u;
-                v0[u] = src[(size_t)sl * T * T + idx];
-                v1[u] = src[(size_t)(sl + 1) * T * T + idx];
+            for (int e = 0; e < SPR; ++e) {
+                const size_t so = (size_t)min(sl + e, PT - 1) * T * T;
+#pragma unroll
+                for (int u = 0; u < CPT; ++u) v[e][u] = src[so + tid + CTH * u];
             }
 #pragma unroll
-            for (int u = 0; u < CPT; ++u) {
-                const uint64_t w = v0[u] < v1[u] ? v0[u] : v1[u];
-                key[u] = w < key[u] ? w : key[u];
-            }
-        }
-        if (sl < PT) {
+            for (int e = 0; e < SPR; ++e)
 #pragma unroll
-            for (int u = 0; u < CPT; ++u) {
-                const uint64_t w = src[(size_t)sl * T * T + tid + CTH * u];
-                key[u] = w < key[u] ? w : key[u];
-            }
+                for (int u = 0; u < CPT; ++u) key[u] = v[e][u] < key[u] ? v[e][u] : key[u];
         }
     }
 #pragma unroll
@@ -716,11 +730,7 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
             }
             const double pJc = L.pJs[cc + 1];
             const double xbulk = (&L.Xt[0][0])[xo + r];
-            // (b) slots the wave's rows can use: c' < c for its last row's c.
-            const int c_top = min(c_hi, nJ - 1);
-            const int tb = c_top >= 1 ? min(CS, (c_top - 1) / G + 1) : 0;
-            const double best =
-                close_step_at<T, G, 0>((h * CROWS) / G, tb, R, L, xo, djb, g, pJc);
+            const double best = close_step_at<T, G, 0>((h * CROWS) / G, R, L, xo, djb, g, pJc);
             const double fin = fmin(best, xbulk);
             const double base = floor(fin * inv_scale);
             const double cost = OB ? base + (pJc - w_row) : base;
@@ -860,15 +870,19 @@ __global__ __launch_bounds__(256) void k_bulk_wide(const TileChain *__restrict__
     const int nJ = min(T, n - col0);
     const int tx = tid % TW, ty = tid / TW;
 
+    // Dims loaded together (clamped column indices), as in k_bulk.
+    int64_t pi4[4], pc4[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) pi4[a] = p[row0 + ty + TW * a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) pc4[b] = p[col0 + min(tx + TW * b, nJ - 1) + 1];
     int64_t pj[4][4], best[4][4];
     int32_t bk[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        const int64_t pi = p[row0 + ty + TW * a];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int c = tx + TW * b;
-            pj[a][b] = c < nJ ? pi * (int64_t)p[col0 + c + 1] : 0;
+            pj[a][b] = tx + TW * b < nJ ? pi4[a] * pc4[b] : 0;
             best[a][b] = INT64_MAX;
             bk[a][b] = k0;
         }

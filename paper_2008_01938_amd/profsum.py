@@ -4,6 +4,7 @@
     python -m paper_2008_01938_amd.profsum counters --evals EVALS_JSON DIR...
     python -m paper_2008_01938_amd.profsum traffic FETCH_DIR WRITE_DIR
     python -m paper_2008_01938_amd.profsum clock CLK_DIR
+    python -m paper_2008_01938_amd.profsum sq [--clock GHZ] [--evals EVALS_JSON] DIR...
 
 DIR is a rocprofv3 ``-d`` directory written with ``--output-format csv``;
 the CSV files are found under it at any depth.  Kernel names are shortened
@@ -185,6 +186,63 @@ def cmd_counters(dirs, evals_json: str | None) -> None:
     print(json.dumps({k: {n: v for n, v in a.items()} for k, a in agg.items()}, indent=None))
 
 
+def cmd_sq(dirs, clock_ghz: float, evals_json: str | None) -> None:
+    """Utilisation figures per kernel from SQ counter runs of one workload
+    (each DIR one rocprofv3 --pmc pass with its kernel trace; a counter's
+    value is taken from the pass that collected it, durations are averaged
+    over the passes):
+      VALU busy (device)  wave VALU instructions x 4 cycles (a wave64
+                          instruction occupies a 16-lane SIMD for four
+                          cycles) over 1024 SIMDs x summed duration x clock;
+      VALU busy (own CUs) the same over 4 SIMDs x SQ_BUSY_CU_CYCLES, i.e.
+                          on the compute units the kernel occupied;
+      LDS bank-conflict cycles over LDS-active cycles;
+      fp64 FMA / ADD wave instructions per 64 split evaluations (when the
+      evaluations per kernel are given)."""
+    evals = {}
+    if evals_json:
+        with open(evals_json) as f:
+            evals = json.load(f)
+    vals = defaultdict(lambda: defaultdict(list))   # kernel -> counter -> per-pass sums
+    for d in dirs:
+        c = counters(d)
+        du = durations(d)
+        per = defaultdict(lambda: defaultdict(float))
+        for did, rec in c.items():
+            a = per[rec["kernel"]]
+            for k, v in rec.items():
+                if k != "kernel":
+                    a[k] += v
+            a["dur_ns"] += du.get(did, 0)
+            a["dispatches"] += 1
+        for kern, a in per.items():
+            for k, v in a.items():
+                vals[kern][k].append(v)
+    tot = {kern: {k: sum(v) / len(v) for k, v in a.items()} for kern, a in vals.items()}
+    print(f"clock used for SIMD-cycles: {clock_ghz:.3f} GHz")
+    print("| kernel | dispatches | VALU wave-instr per dispatch | VALU busy (device) "
+          "| VALU busy (own CUs) | fp64 FMA per 64 evals | fp64 ADD per 64 evals "
+          "| LDS instr per VALU instr | LDS bank-conflict / LDS-active |")
+    print("|---|---|---|---|---|---|---|---|---|")
+    for k in sorted(tot, key=lambda x: -tot[x].get("SQ_INSTS_VALU", 0)):
+        a = tot[k]
+        nd = a["dispatches"]
+        valu = a.get("SQ_INSTS_VALU", 0.0)
+        simd_cycles = 1024 * a["dur_ns"] * 1e-9 * clock_ghz * 1e9
+        busy = 4 * valu / simd_cycles if simd_cycles else float("nan")
+        cu = a.get("SQ_BUSY_CU_CYCLES", 0.0)
+        busy_cu = f"{valu / cu:.3f}" if cu else "-"
+        ev = evals.get(k)
+        fma = f"{a.get('SQ_INSTS_VALU_FMA_F64', 0) * 64 / ev:.3f}" if ev else "-"
+        add = f"{a.get('SQ_INSTS_VALU_ADD_F64', 0) * 64 / ev:.3f}" if ev else "-"
+        lds = a.get("SQ_INSTS_LDS", 0.0)
+        act = a.get("SQ_ACTIVE_INST_LDS", 0.0)
+        conf = a.get("SQ_LDS_BANK_CONFLICT", 0.0)
+        print(f"| {k} | {int(nd)} | {valu / max(nd, 1):.4g} | {busy:.3f} | {busy_cu} | {fma} | "
+              f"{add} | {lds / valu if valu else float('nan'):.3f} | "
+              f"{conf / act if act else float('nan'):.3f} |")
+
+
 def cmd_clock(d: str) -> None:
     """Shader clock while each kernel runs: a least-squares line of
     GRBM_COUNT (summed over the XCDs) against the dispatch's duration."""
@@ -226,6 +284,17 @@ def main(argv) -> int:
         cmd_traffic(argv[2], argv[3])
     elif cmd == "clock":
         cmd_clock(argv[2])
+    elif cmd == "sq":
+        args = argv[2:]
+        clock, ev = 2.4, None
+        while args and args[0].startswith("--"):
+            if args[0] == "--clock":
+                clock, args = float(args[1]), args[2:]
+            elif args[0] == "--evals":
+                ev, args = args[1], args[2:]
+            else:
+                break
+        cmd_sq(args, clock, ev)
     elif cmd == "counters":
         args = argv[2:]
         ev = None
