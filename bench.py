@@ -22,7 +22,10 @@ preallocated.  Prints one JSON line:
              when the kernel source changed since it was taken.
   c1, c2     the n = 128 and n = 2048 chains: median latency over 100 solves
              (HIP events on the stream), and split evaluations/s.
-  batched    4096 chains (n in [16, 512]) in one plan solve vs plain solves.
+  batched    4096 chains (n in [16, 512]) in one plan solve vs plain solves
+             (and the plan replayed from a HIP graph).
+  wide       n = 8192 with dims in [1, 4096]: the int64 tiled kernels and the
+             int64 wavefront.
   serving    the 20000-request Poisson stream at 0.8 x the measured plain
              capacity (and at 2 x, and all at once), served vs plain.
   cpu_baseline  the CPU oracle on a bounded window of the n = 8192 chain on
@@ -251,6 +254,20 @@ def bench_batched(binding, workloads, torch, reps: int = 3):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         best = dt if best is None else min(best, dt)
+    # The same plan replayed from a HIP graph recorded once for these outputs.
+    gstream = torch.cuda.Stream()
+    graph_ms = None
+    with torch.cuda.stream(gstream):
+        plan.graph_create(m_all, s_all, stream=gstream)
+        plan.graph_solve(b.p_all, stream=gstream)
+        gstream.synchronize()
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            plan.graph_solve(b.p_all, stream=gstream)
+            gstream.synchronize()
+            dt = time.perf_counter() - t0
+            graph_ms = 1e3 * dt if graph_ms is None else min(graph_ms, 1e3 * dt)
+    torch.cuda.synchronize()
     plan.close()
     # The one-shot call again: it now starts from the tuning cache's entry
     # for this batch's bucket.
@@ -298,6 +315,7 @@ def bench_batched(binding, workloads, torch, reps: int = 3):
             "plain_instances_per_s": count / plain, "plain_ms": 1e3 * plain,
             "speedup_vs_plain": plain / best,
             "oneshot_ms": 1e3 * oneshot, "oneshot_after_autotune_ms": 1e3 * oneshot_cached,
+            "graph_replay_ms": graph_ms,
             "plan_build_ms": 1e3 * plan_build,
             "autotune": autotune,
             "readback_ms": 1e3 * rb, "readback_costs_equal_m0n": rb_ok,
@@ -387,6 +405,33 @@ def bench_obst(binding, torch, n: int = 8192, reps: int = 3):
         out[f"{algo}_ms"] = 1e3 * best
     L = n + 1
     out["split_evals_per_s"] = (L ** 3 - L) / 6 / (out["tiled_ms"] / 1e3)
+    return out
+
+
+def bench_wide(binding, workloads, torch, reps: int = 3):
+    """n = 8192 with dims uniform in [1, 4096] (seed 4096): (n-1) max(p)^3 is
+    about 2^49, past the fp64 keys' exact range, so AUTO runs the tiled
+    schedule on the int64 kernels; the int64 wavefront beside it."""
+    p = workloads.uniform_dims(8192, 1, 4096, 4096)
+    n = len(p) - 1
+    chain = binding.Chain(p)
+    m = torch.empty((n, n), dtype=torch.int64, device="cuda")
+    s = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    out = {"workload": "n=8192, dims uniform int32 [1,4096], seed 4096 (beyond the fp64 keys)"}
+    for algo, tries in (("auto", reps), ("wavefront", 1)):
+        chain.solve_into(m, s, algo=algo)
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(tries):
+            t0 = time.perf_counter()
+            chain.solve_into(m, s, algo=algo)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        key = "tiled_int64" if algo == "auto" else "wavefront"
+        out[f"{key}_ms"] = 1e3 * best
+        out[f"{key}_split_evals_per_s"] = (n ** 3 - n) / 6 / best
+    chain.close()
     return out
 
 
@@ -505,6 +550,8 @@ def main() -> int:
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--no-sdp", action="store_true", help="skip the S-DP section")
     ap.add_argument("--no-obst", action="store_true", help="skip the optimal-BST section")
+    ap.add_argument("--no-wide", action="store_true",
+                    help="skip the n=8192 dims [1,4096] section (int64 tiled kernels)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the pipeline (Fig. 8) ablation section")
     ap.add_argument("--serve-requests", type=int, default=20000)
@@ -633,6 +680,8 @@ def main() -> int:
         "roofline": roofline,
         "kernels_ms_per_step": {k: round(v["ms"], 4) for k, v in prof.items()},
         "kernels_ms_serial": {k: round(v["ms"], 4) for k, v in prof_serial.items()},
+        "kernels_split_evals_serial": {k: v["split_evals"] for k, v in prof_serial.items()},
+        "kernels_launches_serial": {k: v["launches"] for k, v in prof_serial.items()},
         "serial_solve_ms": round(1e3 * serial_wall, 3),
     }
     progress(f"n={n}: {ms_per_step:.3f} ms per step; serial solve {1e3 * serial_wall:.2f} ms")
@@ -659,6 +708,10 @@ def main() -> int:
     if not args.no_obst:
         out["obst"] = bench_obst(binding, torch)
         progress("obst done")
+    if not args.no_wide:
+        out["wide"] = bench_wide(binding, workloads, torch)
+        progress(f"wide: tiled int64 {out['wide']['tiled_int64_ms']:.2f} ms, "
+                 f"wavefront {out['wide']['wavefront_ms']:.1f} ms")
     if not args.no_pipeline:
         out["pipeline_ablation"] = bench_pipeline(binding, workloads, torch)
         progress("pipeline ablation done")

@@ -87,6 +87,45 @@ def all_trees(lo: int, hi: int):
     return out
 
 
+def obst_tables_by_length(p, q):
+    """obst_tables computed with numpy, one interval length at a time: the
+    same textbook recurrence (w(i, j) = w(i, j-1) + p_j + q_j; e(i, j) the
+    minimum over roots r of e(i, r-1) + e(r+1, j), plus w(i, j); the first
+    minimum, i.e. the smallest root), each length's cells and roots formed
+    as one array, for inputs too large for the pure-Python loops.  Same
+    return layout as obst_tables."""
+    n = len(p)
+    if len(q) != n + 1:
+        raise ValueError("need n+1 gap weights")
+    P = np.concatenate([[0], np.asarray(p, dtype=np.int64)])   # P[i] = p_i
+    Q = np.asarray(q, dtype=np.int64)                           # Q[i] = q_i
+    # E[i][j] holds the textbook e(i, j) for 1 <= i <= n+1, i-1 <= j <= n.
+    E = np.zeros((n + 2, n + 1), dtype=np.int64)
+    W = np.zeros((n + 2, n + 1), dtype=np.int64)
+    R = np.zeros((n + 2, n + 1), dtype=np.int64)
+    idx = np.arange(1, n + 2)
+    E[idx, idx - 1] = Q[idx - 1]
+    W[idx, idx - 1] = Q[idx - 1]
+    for length in range(1, n + 1):
+        i = np.arange(1, n - length + 2)            # every cell of this length
+        j = i + length - 1
+        W[i, j] = W[i, j - 1] + P[j] + Q[j]
+        r = i[:, None] + np.arange(length)[None, :]  # roots i..j per cell
+        cand = E[i[:, None], r - 1] + E[r + 1, j[:, None]]
+        k = np.argmin(cand, axis=1)                   # first minimum: smallest root
+        E[i, j] = cand[np.arange(i.size), k] + W[i, j]
+        R[i, j] = i + k
+    L = n + 1
+    Et = np.zeros((L, L), dtype=np.int64)
+    Rt = np.full((L, L), -1, dtype=np.int32)
+    for a in range(L):
+        b = np.arange(a, L)
+        Et[a, b] = E[a + 1, b]
+        Et[b, a] = E[a + 1, b]
+        Rt[a, b[1:]] = R[a + 1, b[1:]]
+    return Et, Rt
+
+
 def obst_tables(p, q):
     """The (n+1) x (n+1) int64 / int32 tables of the library's layout: gaps
     0..n as leaves; for a <= b, e[a][b] = e(a+1, b) of the textbook (keys

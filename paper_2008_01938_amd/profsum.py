@@ -3,6 +3,7 @@
     python -m paper_2008_01938_amd.profsum stats DIR
     python -m paper_2008_01938_amd.profsum counters --evals EVALS_JSON DIR...
     python -m paper_2008_01938_amd.profsum traffic FETCH_DIR WRITE_DIR
+    python -m paper_2008_01938_amd.profsum trafficfile FETCH_DIR WRITE_DIR KERNEL EVALS TILE SOURCE
     python -m paper_2008_01938_amd.profsum clock CLK_DIR
     python -m paper_2008_01938_amd.profsum sq [--clock GHZ] [--evals EVALS_JSON] DIR...
 
@@ -145,6 +146,37 @@ def cmd_traffic(fetch_dir: str, write_dir: str) -> None:
         print(f"| {k} | {int(nd)} | {fb / 1e6:.2f} | {wb / 1e6:.2f} |")
 
 
+def cmd_trafficfile(fetch_dir: str, write_dir: str, kernel: str, evals: float,
+                    tile: int, source: str) -> None:
+    """The key: value summary bench.py reads for `roofline.traffic`: HBM bytes
+    per dispatch of `kernel` (FETCH_SIZE and WRITE_SIZE scaled as in
+    `traffic`), and the algorithmic operand bytes per dispatch (two 8-byte
+    panel elements per staged split, reused by the tile's `tile` cells of a
+    row or column: 16 / tile bytes per split evaluation) for `evals` split
+    evaluations over all its dispatches.  `source` is the kernel's source
+    file, whose sha256 marks which build the counters belong to."""
+    import hashlib
+    fetch, write = counters(fetch_dir), counters(write_dir)
+    f_agg = per_kernel(fetch, ["FETCH_SIZE"])
+    w_agg = per_kernel(write, ["WRITE_SIZE"])
+    copy_kib = float(1 << 20)
+    f_scale = copy_kib / (f_agg[COPY_KERNEL]["FETCH_SIZE"] / max(f_agg[COPY_KERNEL]["dispatches"], 1))
+    w_scale = copy_kib / (w_agg[COPY_KERNEL]["WRITE_SIZE"] / max(w_agg[COPY_KERNEL]["dispatches"], 1))
+    nd = f_agg[kernel]["dispatches"]
+    fb = f_agg[kernel]["FETCH_SIZE"] * 1024 * f_scale / nd
+    wb = w_agg[kernel]["WRITE_SIZE"] * 1024 * w_scale / max(w_agg[kernel]["dispatches"], 1)
+    with open(source, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    print(f"kernel_source_sha256: {sha}")
+    print(f"fetch_scale: {f_scale:.6f}")
+    print(f"write_scale: {w_scale:.6f}")
+    print(f"bulk_launches: {int(nd)}")
+    print(f"bulk_fetch_bytes_per_launch: {fb:.0f}")
+    print(f"bulk_write_bytes_per_launch: {wb:.0f}")
+    print(f"bulk_hbm_bytes_per_launch: {fb + wb:.0f}")
+    print(f"bulk_algorithmic_operand_bytes_per_launch: {evals * 16.0 / tile / nd:.0f}")
+
+
 def cmd_counters(dirs, evals_json: str | None) -> None:
     """SQ counters per kernel: instruction counts per dispatch, VALU issue
     rate against one wave instruction per CU per cycle, LDS bank-conflict
@@ -280,6 +312,8 @@ def main(argv) -> int:
     cmd = argv[1]
     if cmd == "stats":
         cmd_stats(argv[2])
+    elif cmd == "trafficfile":
+        cmd_trafficfile(argv[2], argv[3], argv[4], float(argv[5]), int(argv[6]), argv[7])
     elif cmd == "traffic":
         cmd_traffic(argv[2], argv[3])
     elif cmd == "clock":

@@ -70,6 +70,30 @@ def test_tiled_range_and_fallback():
 
 
 @pytest.mark.parametrize("algo", ["wavefront", "tiled"])
+def test_n1200_whole_table_against_oracle(algo):
+    # 1201 gaps (19 tiles of 64 per side, a ragged last one), weights below
+    # 2^20: every cell and root against the oracle's by-length form.
+    n = 1200
+    rng = np.random.default_rng(10)
+    p = rng.integers(0, 1 << 20, size=n).astype(np.int32)
+    q = rng.integers(0, 1 << 20, size=n + 1).astype(np.int32)
+    e, r = _solve(p, q, algo)
+    oe, orr = _n1200_oracle(p, q)
+    assert np.array_equal(e, oe) and np.array_equal(r, orr)
+
+
+_ORACLE_CACHE = {}
+
+
+def _n1200_oracle(p, q):
+    key = (p.tobytes(), q.tobytes())
+    if key not in _ORACLE_CACHE:
+        _say("[cpu] optimal-BST oracle n=1200 (by interval length)")
+        _ORACLE_CACHE[key] = interval.obst_tables_by_length(p, q)
+    return _ORACLE_CACHE[key]
+
+
+@pytest.mark.parametrize("algo", ["wavefront", "tiled"])
 def test_large_sampled_recurrence(algo):
     # n = 3000: every sampled cell must satisfy the recurrence over the
     # table's own entries, with the smallest root; the diagonal holds q.

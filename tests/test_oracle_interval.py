@@ -70,3 +70,19 @@ def test_zero_key_weights_only_gaps_count():
         q[g] = 7
         e, _ = interval.optimal_bst([0] * n, q)
         assert e[(1, n)] == (2 if g in (0, n) else 3) * 7
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_by_length_form_equals_textbook_loops(seed):
+    # The numpy by-length form (used for inputs too large for the loops)
+    # against the textbook loops, which the brute force above pins; ties
+    # (small weights) included.
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(0, 45))
+    hi = int(rng.choice([0, 1, 3, 1000, 1 << 20]))
+    p = rng.integers(0, hi + 1, size=n)
+    q = rng.integers(0, hi + 1, size=n + 1)
+    E, R = interval.obst_tables(p, q)
+    E2, R2 = interval.obst_tables_by_length(p, q)
+    assert E2.dtype == E.dtype and R2.dtype == R.dtype
+    assert np.array_equal(E, E2) and np.array_equal(R, R2)
