@@ -59,6 +59,19 @@ constexpr int KC = 16;         // k values staged per LDS round (bulk)
 constexpr int NTH = 256;       // k_tri and k_tri_key threads
 constexpr double kPad = 4611686018427387904.0;  // 2^62: never wins a min
 
+// Wave issue priority 0..3 (s_setprio takes an immediate).
+__device__ __forceinline__ void set_prio(int p)
+{
+    if (p >= 3)
+        __builtin_amdgcn_s_setprio(3);
+    else if (p == 2)
+        __builtin_amdgcn_s_setprio(2);
+    else if (p == 1)
+        __builtin_amdgcn_s_setprio(1);
+    else
+        __builtin_amdgcn_s_setprio(0);
+}
+
 // The segment of a launch that workgroup b belongs to (segments are sorted
 // by their first workgroup; every thread of the workgroup agrees).
 __device__ __forceinline__ int find_seg(const TileSeg *__restrict__ seg, int nseg, int b)
@@ -320,7 +333,8 @@ __global__ __launch_bounds__(bulk_threads<T>()) void k_bulk(const TileChain *__r
                                                             int nseg,
                                                             const int64_t *__restrict__ m_all,
                                                             const double *__restrict__ pd_all,
-                                                            uint64_t *__restrict__ part_all)
+                                                            uint64_t *__restrict__ part_all,
+                                                            int paced)
 {
     constexpr int BTH = bulk_threads<T>();
     constexpr int TW = T / 4;            // threads per microtile row
@@ -425,6 +439,12 @@ __global__ __launch_bounds__(bulk_threads<T>()) void k_bulk(const TileChain *__r
     for (int rd = 0; rd < rounds; ++rd) {
         const int kc = k0 + rd * KC;
         const bool more = rd + 1 < rounds;
+        // paced: issue priority falls as the chunk progresses (3 in its
+        // first quarter, 0 in its last).  The workgroups sharing a CU would
+        // otherwise be served oldest first and finish one after another,
+        // the last alone on the CU with little to hide its latencies.  Not
+        // for launches that share CUs with closures (batched plans).
+        if (paced) set_prio(3 - (4 * rd) / rounds);
         if (more) load(kc + KC);
 #pragma unroll 4
         for (int kk = 0; kk < KC; ++kk) {
@@ -848,7 +868,7 @@ __global__ __launch_bounds__(256) void k_bulk_wide(const TileChain *__restrict__
                                                   const TileSeg *__restrict__ segs, int nseg,
                                                   const int64_t *__restrict__ m_all,
                                                   const int32_t *__restrict__ p_all,
-                                                  int64_t *__restrict__ part_all)
+                                                  int64_t *__restrict__ part_all, int paced)
 {
     constexpr int T = WT, TW = 16, RA = 16, RB = 4, V = 4;
     __shared__ BulkLdsWide L;
@@ -919,6 +939,7 @@ __global__ __launch_bounds__(256) void k_bulk_wide(const TileChain *__restrict__
         const int kc = k0 + rd * KC;
         const bool more = rd + 1 < rounds;
         const int kn = min(KC, kend - kc);  // splits of this round (uniform)
+        if (paced) set_prio(3 - (4 * rd) / rounds);  // as in k_bulk
         if (more) load(kc + KC);
         for (int kk = 0; kk < kn; ++kk) {
             int64_t av[4], bv[4];
@@ -1667,7 +1688,7 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
                                    sg, L.nseg, p, m_all, s_all, nullptr, nullptr, nullptr);
             else if (L.kind == TK_BULK)
                 hipLaunchKernelGGL(k_bulk_wide, dim3(L.blocks), dim3(256), 0, q, chains, sg,
-                                   L.nseg, m_all, p, (int64_t *)part);
+                                   L.nseg, m_all, p, (int64_t *)part, plan.lone ? 1 : 0);
             else
                 hipLaunchKernelGGL(k_close_wide, dim3(L.blocks), dim3(1024),
                                    plan.lone ? kCloseWideExtraLds : 0, q, chains, sg, L.nseg,
@@ -1687,12 +1708,13 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
             e = hipGetLastError();
         } else if (L.kind == TK_BULK) {
             ProfileScope ps(KC_BULK, q, L.evals);
+            const int paced = plan.lone ? 1 : 0;
             if (plan.T == 32)
                 hipLaunchKernelGGL(k_bulk<32>, dim3(L.blocks), dim3(bulk_threads<32>()), 0, q,
-                                   chains, sg, L.nseg, m_all, pd, part);
+                                   chains, sg, L.nseg, m_all, pd, part, paced);
             else
                 hipLaunchKernelGGL(k_bulk<64>, dim3(L.blocks), dim3(bulk_threads<64>()), 0, q,
-                                   chains, sg, L.nseg, m_all, pd, part);
+                                   chains, sg, L.nseg, m_all, pd, part, paced);
             e = hipGetLastError();
         } else if (L.kind == TK_CLOSE) {
             ProfileScope ps(KC_CLOSE, q, L.evals);
