@@ -1278,6 +1278,11 @@ BulkLayout bulk_layout(int32_t T, int32_t NT, int32_t E, int32_t kb, bool lone, 
             }
         }
     }
+    // A lone chain's end blocks run on the closure's CUs right after it,
+    // one or two workgroups per CU: chunks of at most 32 splits halve each
+    // workgroup's latency-bound run (measured faster than the model's pick
+    // of one 64-split chunk per range).
+    if (fit && !serial && end_ks > 2 * KC) end_ks = 2 * KC;
     if (end_ks > cap) end_ks = cap;
     bl.end_ks = end_ks;
     bl.end_nch = (end_len + end_ks - 1) / end_ks;
