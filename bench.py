@@ -102,7 +102,7 @@ def read_sclk():
     with open(SCLK_FILE) as f:
         for line in f:
             cells = [c.strip() for c in line.strip().strip("|").split("|")]
-            if len(cells) >= 4 and cells[0] == "k_bulk":
+            if len(cells) >= 4 and cells[0] in ("k_bulk", "k_bulk<64>"):
                 try:
                     return float(cells[3])
                 except ValueError:
