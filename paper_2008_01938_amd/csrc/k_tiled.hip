@@ -59,6 +59,18 @@ constexpr int KC = 16;         // k values staged per LDS round (bulk)
 constexpr int NTH = 256;       // k_tri and k_tri_key threads
 constexpr double kPad = 4611686018427387904.0;  // 2^62: never wins a min
 
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// x * 2^kb as a double for a table entry x in [0, 2^52), given as its two
+// 32-bit halves: setting the exponent field of 2^52 over x's bits gives the
+// double 2^52 + x exactly, and one fma scales it and removes the 2^52 with a
+// single, exact rounding (the result is below 2^53).
+__device__ __forceinline__ double cost_key(u32x2 x, double scale)
+{
+    const double t = __builtin_bit_cast(double, (u32x2){x.x, x.y | 0x43300000u});
+    return fma(t, scale, -4503599627370496.0 * scale);
+}
+
 // Wave issue priority 0..3 (s_setprio takes an immediate).
 __device__ __forceinline__ void set_prio(int p)
 {
@@ -276,8 +288,8 @@ constexpr int dj_packed_size() { return dj_packed_base(T - 1) + T; }
 
 template <int T>
 struct BulkLds {
-    double As[2][KC][T + 1];  // As[kk][r] = m[row0+r][k] * 2^kb
-    double Bs[2][KC][T];      // Bs[kk][c] = m[k+1][col0+c] * 2^kb + (k - k0)
+    double As[2][KC][T + 1];  // As[kk][r] = m[row0+r][k] * 2^kb + (k - k0)
+    double Bs[2][KC][T];      // Bs[kk][c] = m[k+1][col0+c] * 2^kb
     double Ps[2][KC];         // p[k+1]
 };
 
@@ -327,14 +339,13 @@ struct CloseLdsPacked {
 template <int T>
 constexpr int bulk_threads() { return (T / 4) * (T / 4); }
 
+// 64-edge tiles: held to three waves per SIMD (at most 168 VGPRs), which
+// the kernel fits without spills; the 32-edge form runs at two.
 template <int T>
-__global__ __launch_bounds__(bulk_threads<T>()) void k_bulk(const TileChain *__restrict__ chains,
-                                                            const TileSeg *__restrict__ segs,
-                                                            int nseg,
-                                                            const int64_t *__restrict__ m_all,
-                                                            const double *__restrict__ pd_all,
-                                                            uint64_t *__restrict__ part_all,
-                                                            int paced)
+__global__ __launch_bounds__(bulk_threads<T>()) __attribute__((amdgpu_waves_per_eu(T == 64 ? 3 : 2)))
+void k_bulk(const TileChain *__restrict__ chains, const TileSeg *__restrict__ segs, int nseg,
+            const int64_t *__restrict__ m_all, const double *__restrict__ pd_all,
+            uint64_t *__restrict__ part_all, int paced)
 {
     constexpr int BTH = bulk_threads<T>();
     constexpr int TW = T / 4;            // threads per microtile row
@@ -388,7 +399,8 @@ __global__ __launch_bounds__(bulk_threads<T>()) void k_bulk(const TileChain *__r
     // bkk + RB*v at column bc (v < V).  Only the round's base moves, so on a
     // table under 2 GiB the loads take 32-bit byte offsets from a uniform
     // base.  In a round that passes kend, splits at or past it are staged
-    // from split kend-1 (inside the table) and masked.
+    // from split kend-1 (inside the table) and masked.  (Raw buffer loads
+    // with the same offsets measured slower.)
     const int akk = tid % KC, ar = tid / KC;
     const int bcol = tid % T, bc = min(bcol, nJ - 1), bkk = tid / T;
     const bool narrow = (size_t)n * (size_t)n * sizeof(int64_t) < ((size_t)1 << 31);
@@ -398,7 +410,9 @@ __global__ __launch_bounds__(bulk_threads<T>()) void k_bulk(const TileChain *__r
         oa[v] = (uint32_t)(((size_t)(row0 + ar + RA * v) * n + akk) * sizeof(int64_t));
         ob[v] = (uint32_t)(((size_t)(bkk + RB * v + 1) * n + col0 + bc) * sizeof(int64_t));
     }
-    int64_t ra[V], rb[V];
+    // Table entries as two 32-bit halves; every entry staged is a cost of a
+    // final cell, below 2^46, which the store turns into a key exactly.
+    u32x2 ra[V], rb[V];
     double rp = 0.0;
     auto load = [&](int kc) {
         if (kc + KC <= kend && narrow) {
@@ -406,29 +420,37 @@ __global__ __launch_bounds__(bulk_threads<T>()) void k_bulk(const TileChain *__r
             const char *bb = (const char *)(m + (size_t)kc * n);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                ra[v] = *(const int64_t *)(ba + oa[v]);
-                rb[v] = *(const int64_t *)(bb + ob[v]);
+                ra[v] = *(const u32x2 *)(ba + oa[v]);
+                rb[v] = *(const u32x2 *)(bb + ob[v]);
             }
         } else {
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const int ka = min(kc + akk, kend - 1);
-                ra[v] = m[(size_t)(row0 + ar + RA * v) * n + ka];
+                ra[v] = __builtin_bit_cast(u32x2, m[(size_t)(row0 + ar + RA * v) * n + ka]);
                 const int kb2 = min(kc + bkk + RB * v, kend - 1);
-                rb[v] = m[(size_t)(kb2 + 1) * n + col0 + bc];
+                rb[v] = __builtin_bit_cast(u32x2, m[(size_t)(kb2 + 1) * n + col0 + bc]);
             }
         }
         if (tid < KC) rp = (kc + tid < kend) ? pd[kc + tid + 1] : 0.0;
     };
+    // The A side carries the split's offset from k0 (one split per thread
+    // and round: akk), so A keys are cost * 2^kb + (k - k0) and B keys
+    // cost * 2^kb; their sum is the same key.
     auto store = [&](int kc, int buf) {
-        const bool full = kc + KC <= kend;
+        const double koff = (double)(kc + akk - k0);
+        if (kc + KC <= kend) {
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            L.As[buf][akk][ar + RA * v] =
-                (full || kc + akk < kend) ? (double)ra[v] * scale : kPad;
-            L.Bs[buf][bkk + RB * v][bcol] =
-                fma((double)rb[v], scale, (double)(kc + bkk + RB * v - k0));
+            for (int v = 0; v < V; ++v)
+                L.As[buf][akk][ar + RA * v] = cost_key(ra[v], scale) + koff;
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                L.As[buf][akk][ar + RA * v] =
+                    kc + akk < kend ? cost_key(ra[v], scale) + koff : kPad;
         }
+#pragma unroll
+        for (int v = 0; v < V; ++v) L.Bs[buf][bkk + RB * v][bcol] = cost_key(rb[v], scale);
         if (tid < KC) L.Ps[buf][tid] = rp;
     };
 
