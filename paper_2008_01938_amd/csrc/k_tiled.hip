@@ -1251,10 +1251,12 @@ namespace {
 // Estimated duration, in split units, of `units` equal workgroups of `ks`
 // splits each on `slots` resident workgroup slots: whole waves of
 // workgroups, each paying about one staged round of fixed cost.
-// Duration of a lone chain's closure in split times of a bulk workgroup
-// (a closure sweep takes about as long as a resident bulk workgroup needs
-// for this many splits).
-constexpr int32_t kCloseSplits = 256;
+// When a lone chain's closure CUs take up bulk work again, in split times
+// of a bulk workgroup.  The sweep itself takes about 250 of them; 192
+// (tier-2 chunks planned to start somewhat early, so somewhat longer)
+// measured best, 2.2% faster at n = 8192 than 256, with 224 within noise
+// and 128 3% slower.
+constexpr int32_t kCloseSplits = 192;
 
 double wave_cost(int64_t units, int32_t ks, int64_t slots)
 {
@@ -1333,11 +1335,17 @@ BulkLayout bulk_layout(int32_t T, int32_t NT, int32_t E, int32_t kb, bool lone, 
         bl.int_len = L;
         if (fit && !serial) {
             // Alternative: one wave of long chunks on the interior's slots,
-            // then one wave of short chunks that start on the closure's CUs
-            // once the closure is done (it takes about kCloseSplits split
-            // times of a bulk workgroup); both waves should end together.
+            // then short chunks that start on the closure's CUs once the
+            // closure is done (kCloseSplits); both tiers should end
+            // together.  The short tier gets one and a third chunks per
+            // closure-CU slot: those slots also run the end blocks, which
+            // are short, and a queue a third deep keeps them busy after.
+            // (Half a chunk per slot, the first choice, left the closure
+            // CUs idle for most of a middle tile-diagonal's interior:
+            // 17.5 -> 16.9 ms at n = 8192 with this and kCloseSplits.)
             const double single = wave_cost((int64_t)tiles * bl.int_nch, ks, slots_int);
-            const int64_t nb64 = slots_int / tiles, ns64 = slots_end / 2 / tiles;
+            const int64_t nb64 = slots_int / tiles;
+            const int64_t ns64 = (slots_end + slots_end / 3) / tiles;
             const int32_t nb = (int32_t)(nb64 < kMaxChunks ? nb64 : kMaxChunks);
             const int32_t ns = (int32_t)(ns64 < kMaxChunks - nb ? ns64 : kMaxChunks - nb);
             if (nb >= 1 && ns >= 1) {
