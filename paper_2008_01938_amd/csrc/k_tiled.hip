@@ -883,9 +883,12 @@ constexpr int WT = 64;
 struct BulkLdsWide {
     int64_t As[2][KC][WT + 1];  // m[row0+r][k]
     int64_t Bs[2][KC][WT];      // m[k+1][col0+c]
-    int64_t Ps[2][KC];          // p[k+1]
+    uint32_t Ps[2][KC];         // p[k+1] (a dimension: positive int32)
 };
 
+// PJ32: every dimension is below 2^16, so p_i p_j fits 32 bits and the
+// product term p_i p_j p[k+1] is one 32 x 32 -> 64-bit multiply.
+template <bool PJ32>
 __global__ __launch_bounds__(256) void k_bulk_wide(const TileChain *__restrict__ chains,
                                                   const TileSeg *__restrict__ segs, int nseg,
                                                   const int64_t *__restrict__ m_all,
@@ -918,13 +921,15 @@ __global__ __launch_bounds__(256) void k_bulk_wide(const TileChain *__restrict__
     for (int a = 0; a < 4; ++a) pi4[a] = p[row0 + ty + TW * a];
 #pragma unroll
     for (int b = 0; b < 4; ++b) pc4[b] = p[col0 + min(tx + TW * b, nJ - 1) + 1];
-    int64_t pj[4][4], best[4][4];
+    using PJ = typename std::conditional<PJ32, uint32_t, uint64_t>::type;
+    PJ pj[4][4];
+    int64_t best[4][4];
     int32_t bk[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            pj[a][b] = tx + TW * b < nJ ? pi4[a] * pc4[b] : 0;
+            pj[a][b] = tx + TW * b < nJ ? (PJ)(pi4[a] * pc4[b]) : (PJ)0;
             best[a][b] = INT64_MAX;
             bk[a][b] = k0;
         }
@@ -933,7 +938,8 @@ __global__ __launch_bounds__(256) void k_bulk_wide(const TileChain *__restrict__
     // (inside the table) and never evaluated.
     const int akk = tid % KC, ar = tid / KC;
     const int bcol = tid % T, bc = min(bcol, nJ - 1), bkk = tid / T;
-    int64_t ra[V], rb[V], rp = 0;
+    int64_t ra[V], rb[V];
+    uint32_t rp = 0;
     auto load = [&](int kc) {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -942,7 +948,7 @@ __global__ __launch_bounds__(256) void k_bulk_wide(const TileChain *__restrict__
             const int kb2 = min(kc + bkk + RB * v, kend - 1);
             rb[v] = m[(size_t)(kb2 + 1) * n + col0 + bc];
         }
-        if (tid < KC) rp = p[min(kc + tid, kend - 1) + 1];
+        if (tid < KC) rp = (uint32_t)p[min(kc + tid, kend - 1) + 1];
     };
     auto store = [&](int buf) {
 #pragma unroll
@@ -969,13 +975,16 @@ __global__ __launch_bounds__(256) void k_bulk_wide(const TileChain *__restrict__
             for (int a = 0; a < 4; ++a) av[a] = L.As[buf][kk][ty + TW * a];
 #pragma unroll
             for (int b = 0; b < 4; ++b) bv[b] = L.Bs[buf][kk][tx + TW * b];
-            const int64_t pk = L.Ps[buf][kk];
+            // p[k+1] fits 32 bits, so the product term is a 64 x 32-bit
+            // multiply, or 32 x 32 with PJ32 (integer multiplies are quarter
+            // rate).
+            const uint64_t pk = L.Ps[buf][kk];
             // Splits arrive in increasing k, so a strict < keeps the smallest.
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    const int64_t c = pj[a][b] * pk + bv[b] + av[a];
+                    const int64_t c = (int64_t)((uint64_t)pj[a][b] * pk) + bv[b] + av[a];
                     if (c < best[a][b]) {
                         best[a][b] = c;
                         bk[a][b] = kc + kk;
@@ -1024,7 +1033,7 @@ struct CloseLdsWide {
     int64_t DJ[WT][WT + 1];  // DJ[c][q] = m[col0+q][col0+c] (1 <= q <= c)
     int64_t X[WT][WT + 1];   // X[c][q]: bulk minimum, then final cost of cell (q, c)
     int32_t K[WT][WT + 1];   // its split
-    int64_t pJ[WT + 1];      // p[col0 + q]
+    uint32_t pJ[WT + 1];     // p[col0 + q] (a dimension: positive int32)
 };
 
 // The closure of one 64-edge tile on int64: row group r (16 lanes) sweeps
@@ -1032,6 +1041,9 @@ struct CloseLdsWide {
 // (a) splits, then (lane 0) the bulk minimum, then its (b) splits, in
 // increasing split order with a strict <, so its pair is the lexicographic
 // minimum of its splits; four DPP steps combine the 16 lanes.
+// PJ32: as in k_bulk_wide, p_i p[k+1] fits 32 bits and every product term
+// is one 32 x 32 -> 64-bit multiply on the sweep's critical path.
+template <bool PJ32>
 __global__ __launch_bounds__(1024) void k_close_wide(const TileChain *__restrict__ chains,
                                                     const TileSeg *__restrict__ segs, int nseg,
                                                     int64_t *__restrict__ m_all,
@@ -1058,18 +1070,20 @@ __global__ __launch_bounds__(1024) void k_close_wide(const TileChain *__restrict
 
     // Lane g of row r holds the (a) splits q = t*G + g (r <= q <= T-2) and
     // the (b) splits c' = t*G + g.
-    int64_t DIr[CS], PIr[CS], PJr[CS], Xrow[CS];
+    using PP = typename std::conditional<PJ32, uint32_t, uint64_t>::type;
+    int64_t DIr[CS], Xrow[CS];
+    PP PIr[CS], PJr[CS];
     const int64_t pi = p[row0 + r];
 #pragma unroll
     for (int t = 0; t < CS; ++t) {
         const int q = t * G + g;
         const bool qa = q >= r && q <= T - 2;
         DIr[t] = qa ? m[(size_t)(row0 + r) * n + row0 + q] : 0;
-        PIr[t] = qa ? pi * (int64_t)p[row0 + q + 1] : 0;
-        PJr[t] = q < nJ ? pi * (int64_t)p[col0 + q + 1] : 0;
+        PIr[t] = qa ? (PP)(pi * (int64_t)p[row0 + q + 1]) : (PP)0;
+        PJr[t] = q < nJ ? (PP)(pi * (int64_t)p[col0 + q + 1]) : (PP)0;
         Xrow[t] = 0;
     }
-    for (int q = tid; q <= T; q += CTH) L.pJ[q] = q <= nJ ? p[col0 + q] : 0;
+    for (int q = tid; q <= T; q += CTH) L.pJ[q] = q <= nJ ? (uint32_t)p[col0 + q] : 0u;
     for (int idx = tid; idx < T * T; idx += CTH) {
         const int qq = idx / T, c = idx % T;
         if (qq >= 1 && qq <= c && c < nJ) L.DJ[c][qq] = m[(size_t)(col0 + qq) * n + col0 + c];
@@ -1114,14 +1128,14 @@ __global__ __launch_bounds__(1024) void k_close_wide(const TileChain *__restrict
         const int c_hi = c_lo + CROWS - 1;
         if (c_hi >= 0 && c_lo < nJ) {  // wave-uniform
             const int cc = min(max(c, 0), nJ - 1);
-            const int64_t pJc = L.pJ[cc + 1];
+            const uint64_t pJc = L.pJ[cc + 1];
             int64_t best = INT64_MAX;
             int32_t bk = INT32_MAX;
 #pragma unroll
             for (int t = 0; t < CS; ++t) {  // (a): k = row0 + q, increasing in t
                 const int q = t * G + g;
                 if (q >= r && q <= T - 2) {
-                    const int64_t v = DIr[t] + L.X[cc][q + 1] + PIr[t] * pJc;
+                    const int64_t v = DIr[t] + L.X[cc][q + 1] + (int64_t)((uint64_t)PIr[t] * pJc);
                     if (v < best) {
                         best = v;
                         bk = row0 + q;
@@ -1139,7 +1153,7 @@ __global__ __launch_bounds__(1024) void k_close_wide(const TileChain *__restrict
             for (int t = 0; t < CS; ++t) {  // (b): k = col0 + c', increasing in t
                 const int cp = t * G + g;
                 if (cp < cc) {
-                    const int64_t v = Xrow[t] + L.DJ[cc][cp + 1] + PJr[t] * pJc;
+                    const int64_t v = Xrow[t] + L.DJ[cc][cp + 1] + (int64_t)((uint64_t)PJr[t] * pJc);
                     if (v < best) {
                         best = v;
                         bk = col0 + cp;
@@ -1440,6 +1454,7 @@ int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t 
     c.kb = plan.wide ? 30 : 53 - ci.cost_bits;
     if (!plan.wide && c.kb > 20) c.kb = 20;
     c.kbits = bitlen_u64((uint64_t)(ci.n > 1 ? ci.n - 1 : 1));
+    if (ci.pmax > plan.pmax) plan.pmax = ci.pmax;
     plan.chains.push_back(c);
     plan.NT.push_back(tiled_nt(ci.n, plan.T));
     return (int)plan.chains.size() - 1;
@@ -1721,11 +1736,18 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
             if (L.kind == TK_TRI)
                 hipLaunchKernelGGL((k_tri<64, false>), dim3(L.blocks), dim3(NTH), 0, q, chains,
                                    sg, L.nseg, p, m_all, s_all, nullptr, nullptr, nullptr);
-            else if (L.kind == TK_BULK)
-                hipLaunchKernelGGL(k_bulk_wide, dim3(L.blocks), dim3(256), 0, q, chains, sg,
+            else if (L.kind == TK_BULK && plan.pmax < 65536)
+                hipLaunchKernelGGL(k_bulk_wide<true>, dim3(L.blocks), dim3(256), 0, q, chains, sg,
                                    L.nseg, m_all, p, (int64_t *)part, plan.lone ? 1 : 0);
+            else if (L.kind == TK_BULK)
+                hipLaunchKernelGGL(k_bulk_wide<false>, dim3(L.blocks), dim3(256), 0, q, chains,
+                                   sg, L.nseg, m_all, p, (int64_t *)part, plan.lone ? 1 : 0);
+            else if (plan.pmax < 65536)
+                hipLaunchKernelGGL(k_close_wide<true>, dim3(L.blocks), dim3(1024),
+                                   plan.lone ? kCloseWideExtraLds : 0, q, chains, sg, L.nseg,
+                                   m_all, s_all, p, (const int64_t *)part);
             else
-                hipLaunchKernelGGL(k_close_wide, dim3(L.blocks), dim3(1024),
+                hipLaunchKernelGGL(k_close_wide<false>, dim3(L.blocks), dim3(1024),
                                    plan.lone ? kCloseWideExtraLds : 0, q, chains, sg, L.nseg,
                                    m_all, s_all, p, (const int64_t *)part);
             e = hipGetLastError();

@@ -83,6 +83,19 @@ def test_wide_all_equal_closed_form():
     assert int(mh[0, n - 1]) == (n - 1) * d ** 3 and int(mh[0, n - 1]) < (1 << 63)
 
 
+@pytest.mark.parametrize("top", [65535, 65536])
+def test_wide_dims_at_the_32bit_product_bound(top):
+    # Below 2^16 every product p_i p_k fits 32 bits and the kernels take the
+    # 32 x 32-bit multiply; at 2^16 they take the 64 x 32-bit one.  Both
+    # sides of the bound, dims in [top/2, top] and one dim equal to top.
+    n = 300
+    p = workloads.uniform_dims(n, top // 2, top, 6500 + top % 7)
+    p[n // 3] = top
+    assert (n - 1) * top ** 3 >= (1 << 46) and (n - 1) * top ** 3 < (1 << 63)
+    assert binding.select_algo(p) == binding.ALGO_TILED
+    check(p)
+
+
 def test_wide_matches_wavefront_path():
     import torch
     p = workloads.uniform_dims(333, 1, pmax_for(333), 77)
