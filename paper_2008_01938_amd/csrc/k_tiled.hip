@@ -886,6 +886,148 @@ struct BulkLdsWide {
     uint32_t Ps[2][KC];         // p[k+1] (a dimension: positive int32)
 };
 
+// Chains past the fp64 keys' range whose costs still stay below 2^53
+// ((n-1) max(p)^3 < 2^53): every cost, product term and partial sum is an
+// exact fp64 integer, but no bits remain below the cost for the split, so
+// each thread carries the split of its minima beside them (a compare and a
+// select more per evaluation than k_bulk; still no integer multiply).  The
+// same tiles, chunks and staging as k_bulk; writes the (cost, split) pairs
+// of k_bulk_wide, which the int64 closure merges.
+__device__ __forceinline__ double cost53(u32x2 x)
+{
+    // x < 2^53: both halves convert exactly, and so does their sum.
+    return fma((double)x.y, 4294967296.0, (double)x.x);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+void k_bulk_mid(const TileChain *__restrict__ chains, const TileSeg *__restrict__ segs, int nseg,
+                const int64_t *__restrict__ m_all, const double *__restrict__ pd_all,
+                int64_t *__restrict__ part_all, int paced)
+{
+    constexpr int T = 64, BTH = 256, TW = 16, RA = 16, RB = 4, V = 4;
+    __shared__ BulkLds<64> L;  // As, Bs: costs; Ps: p[k+1]
+    const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
+    const TileChain ch = chains[sg.chain];
+    const int local = blockIdx.x - sg.first;
+    const int32_t n = ch.n, D = sg.D, KS = sg.KS;
+    const int64_t *__restrict__ m = m_all + ch.m_off;
+    const double *__restrict__ pd = pd_all + ch.pd_off;
+    const int tid = threadIdx.x;
+    const int tile = local / sg.nch;
+    const int chunk = local - tile * sg.nch;
+    const int I = tile, J = tile + D;
+    const int row0 = I * T, col0 = J * T;
+    const int kbase = (I + 1) * T - 1 + sg.koff;
+    const int k0 = kbase + chunk * KS;
+    const int kend = min(k0 + KS, kbase + sg.klen);  // exclusive
+    const int rounds = (kend - k0 + KC - 1) / KC;
+    const int nJ = min(T, n - col0);
+    const int tx = tid % TW, ty = tid / TW;
+
+    double pi4[4], pc4[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) pi4[a] = pd[row0 + ty + TW * a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) pc4[b] = pd[col0 + min(tx + TW * b, nJ - 1) + 1];
+    double pj[4][4], best[4][4];
+    int32_t bk[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            pj[a][b] = tx + TW * b < nJ ? pi4[a] * pc4[b] : 0.0;
+            best[a][b] = __builtin_inf();
+            bk[a][b] = k0;
+        }
+    }
+    // Staging as in k_bulk (same per-thread map, 32-bit offsets on a table
+    // under 2 GiB); splits at or past kend are staged from kend-1 and padded
+    // with 2^62 on the A side, so they never win.
+    const int akk = tid % KC, ar = tid / KC;
+    const int bcol = tid % T, bc = min(bcol, nJ - 1), bkk = tid / T;
+    const bool narrow = (size_t)n * (size_t)n * sizeof(int64_t) < ((size_t)1 << 31);
+    uint32_t oa[V], ob[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        oa[v] = (uint32_t)(((size_t)(row0 + ar + RA * v) * n + akk) * sizeof(int64_t));
+        ob[v] = (uint32_t)(((size_t)(bkk + RB * v + 1) * n + col0 + bc) * sizeof(int64_t));
+    }
+    u32x2 ra[V], rb[V];
+    double rp = 0.0;
+    auto load = [&](int kc) {
+        if (kc + KC <= kend && narrow) {
+            const char *ba = (const char *)(m + kc);
+            const char *bb = (const char *)(m + (size_t)kc * n);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                ra[v] = *(const u32x2 *)(ba + oa[v]);
+                rb[v] = *(const u32x2 *)(bb + ob[v]);
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int ka = min(kc + akk, kend - 1);
+                ra[v] = __builtin_bit_cast(u32x2, m[(size_t)(row0 + ar + RA * v) * n + ka]);
+                const int kb2 = min(kc + bkk + RB * v, kend - 1);
+                rb[v] = __builtin_bit_cast(u32x2, m[(size_t)(kb2 + 1) * n + col0 + bc]);
+            }
+        }
+        if (tid < KC) rp = (kc + tid < kend) ? pd[kc + tid + 1] : 0.0;
+    };
+    auto store = [&](int kc, int buf) {
+        const bool full = kc + KC <= kend;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            L.As[buf][akk][ar + RA * v] = (full || kc + akk < kend) ? cost53(ra[v]) : kPad;
+            L.Bs[buf][bkk + RB * v][bcol] = cost53(rb[v]);
+        }
+        if (tid < KC) L.Ps[buf][tid] = rp;
+    };
+
+    load(k0);
+    store(k0, 0);
+    __syncthreads();
+    int buf = 0;
+    for (int rd = 0; rd < rounds; ++rd) {
+        const int kc = k0 + rd * KC;
+        const bool more = rd + 1 < rounds;
+        if (paced) set_prio(3 - (4 * rd) / rounds);  // as in k_bulk
+        if (more) load(kc + KC);
+#pragma unroll 4
+        for (int kk = 0; kk < KC; ++kk) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = L.As[buf][kk][ty + TW * a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = L.Bs[buf][kk][tx + TW * b];
+            const double pk = L.Ps[buf][kk];
+            // Splits arrive in increasing k, so a strict < keeps the smallest.
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const double v = fma(pj[a][b], pk, bv[b]) + av[a];
+                    bk[a][b] = v < best[a][b] ? kc + kk : bk[a][b];
+                    best[a][b] = fmin(best[a][b], v);
+                }
+        }
+        if (more) store(kc + KC, buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+
+    int64_t *out = part_all + sg.part_off + ((size_t)tile * sg.PT + sg.slot0 + chunk) * 2 * T * T;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int r = ty + TW * a, c = tx + TW * b;
+            out[r * T + c] = c < nJ ? (int64_t)best[a][b] : INT64_MAX;
+            out[T * T + r * T + c] = bk[a][b];
+        }
+    }
+}
+
 // PJ32: every dimension is below 2^16, so p_i p_j fits 32 bits and the
 // product term p_i p_j p[k+1] is one 32 x 32 -> 64-bit multiply.
 template <bool PJ32>
@@ -1455,6 +1597,7 @@ int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t 
     if (!plan.wide && c.kb > 20) c.kb = 20;
     c.kbits = bitlen_u64((uint64_t)(ci.n > 1 ? ci.n - 1 : 1));
     if (ci.pmax > plan.pmax) plan.pmax = ci.pmax;
+    if (ci.cost_bits > plan.cost_bits) plan.cost_bits = ci.cost_bits;
     plan.chains.push_back(c);
     plan.NT.push_back(tiled_nt(ci.n, plan.T));
     return (int)plan.chains.size() - 1;
@@ -1736,6 +1879,9 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
             if (L.kind == TK_TRI)
                 hipLaunchKernelGGL((k_tri<64, false>), dim3(L.blocks), dim3(NTH), 0, q, chains,
                                    sg, L.nseg, p, m_all, s_all, nullptr, nullptr, nullptr);
+            else if (L.kind == TK_BULK && plan.cost_bits <= 53)
+                hipLaunchKernelGGL(k_bulk_mid, dim3(L.blocks), dim3(256), 0, q, chains, sg,
+                                   L.nseg, m_all, pd, (int64_t *)part, plan.lone ? 1 : 0);
             else if (L.kind == TK_BULK && plan.pmax < 65536)
                 hipLaunchKernelGGL(k_bulk_wide<true>, dim3(L.blocks), dim3(256), 0, q, chains, sg,
                                    L.nseg, m_all, p, (int64_t *)part, plan.lone ? 1 : 0);

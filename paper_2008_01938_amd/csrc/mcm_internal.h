@@ -273,6 +273,7 @@ struct TiledPlan {
     int pair_min_blocks = 0;           // closures with more workgroups use the paired
                                        // shape; 0: the device's CU count
     int32_t pmax = 0;                  // largest dimension of any chain
+    int32_t cost_bits = 0;             // largest cost_bits of any chain
     bool uses_aux = false;             // some launch runs on the aux stream
     int last_main = -1;                // latest launch on the caller's stream
     int last_close = -1;               // latest closure launch

@@ -96,6 +96,20 @@ def test_wide_dims_at_the_32bit_product_bound(top):
     check(p)
 
 
+@pytest.mark.parametrize("over", [0, 1])
+def test_wide_costs_at_the_2_53_bound(over):
+    # (n-1) max(p)^3 just below 2^53: costs are exact fp64 integers and the
+    # bulk runs in fp64, carrying the split beside the cost; one above: the
+    # int64 bulk.  Dims in [d/2, d], one dim equal to d.
+    n = 200
+    d = pmax_for(n, 53) + over
+    p = workloads.uniform_dims(n, d // 2, d, 6600 + over)
+    p[n // 2] = d
+    assert ((n - 1) * d ** 3 < (1 << 53)) == (over == 0)
+    assert (n - 1) * d ** 3 >= (1 << 46)
+    check(p)
+
+
 def test_wide_matches_wavefront_path():
     import torch
     p = workloads.uniform_dims(333, 1, pmax_for(333), 77)
