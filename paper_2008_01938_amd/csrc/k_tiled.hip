@@ -1171,6 +1171,18 @@ __device__ __forceinline__ void dpp_pair_min(int64_t &c, int32_t &k)
     }
 }
 
+// Minimum of a 64-bit key with the same lane's key in the DPP pattern.
+template <int CTRL>
+__device__ __forceinline__ int64_t dpp_key_min(int64_t v)
+{
+    const int2 b = __builtin_bit_cast(int2, v);
+    int2 o;
+    o.x = __builtin_amdgcn_mov_dpp(b.x, CTRL, 0xF, 0xF, false);
+    o.y = __builtin_amdgcn_mov_dpp(b.y, CTRL, 0xF, 0xF, false);
+    const int64_t ov = __builtin_bit_cast(int64_t, o);
+    return ov < v ? ov : v;
+}
+
 struct CloseLdsWide {
     int64_t DJ[WT][WT + 1];  // DJ[c][q] = m[col0+q][col0+c] (1 <= q <= c)
     int64_t X[WT][WT + 1];   // X[c][q]: bulk minimum, then final cost of cell (q, c)
@@ -1185,7 +1197,12 @@ struct CloseLdsWide {
 // minimum of its splits; four DPP steps combine the 16 lanes.
 // PJ32: as in k_bulk_wide, p_i p[k+1] fits 32 bits and every product term
 // is one 32 x 32 -> 64-bit multiply on the sweep's critical path.
-template <bool PJ32>
+// KEYED: every cost is below 2^54, so the sweep carries int64 keys
+// cost * 2^7 + k_local as the fp64 closure does (k_local: q for (a) splits,
+// T-1 for the bulk, T + c' for (b) splits, increasing with k), and one
+// 64-bit min replaces the (cost, split) pair comparison; slots that do not
+// apply hold 2^62 (above every key, and two keys plus it stay below 2^63).
+template <bool PJ32, bool KEYED>
 __global__ __launch_bounds__(1024) void k_close_wide(const TileChain *__restrict__ chains,
                                                     const TileSeg *__restrict__ segs, int nseg,
                                                     int64_t *__restrict__ m_all,
@@ -1213,6 +1230,8 @@ __global__ __launch_bounds__(1024) void k_close_wide(const TileChain *__restrict
     // Lane g of row r holds the (a) splits q = t*G + g (r <= q <= T-2) and
     // the (b) splits c' = t*G + g.
     using PP = typename std::conditional<PJ32, uint32_t, uint64_t>::type;
+    constexpr int KB = 7;                                // key bits below the cost
+    constexpr int64_t kKeyPad = (int64_t)1 << 62;
     int64_t DIr[CS], Xrow[CS];
     PP PIr[CS], PJr[CS];
     const int64_t pi = p[row0 + r];
@@ -1220,15 +1239,29 @@ __global__ __launch_bounds__(1024) void k_close_wide(const TileChain *__restrict
     for (int t = 0; t < CS; ++t) {
         const int q = t * G + g;
         const bool qa = q >= r && q <= T - 2;
-        DIr[t] = qa ? m[(size_t)(row0 + r) * n + row0 + q] : 0;
+        const int64_t dm = m[(size_t)(row0 + r) * n + row0 + min(q, T - 2)];
+        if constexpr (KEYED)
+            DIr[t] = qa ? (dm << KB) + q : kKeyPad;
+        else
+            DIr[t] = qa ? dm : 0;
         PIr[t] = qa ? (PP)(pi * (int64_t)p[row0 + q + 1]) : (PP)0;
         PJr[t] = q < nJ ? (PP)(pi * (int64_t)p[col0 + q + 1]) : (PP)0;
-        Xrow[t] = 0;
+        Xrow[t] = KEYED ? kKeyPad : 0;
     }
     for (int q = tid; q <= T; q += CTH) L.pJ[q] = q <= nJ ? (uint32_t)p[col0 + q] : 0u;
+    if constexpr (KEYED) {
+        // Every entry a keyed sweep may read, including those whose terms
+        // lose, holds a key below 2^61: no sum can overflow.
+        for (int idx = tid; idx < T * (T + 1); idx += CTH) {
+            (&L.DJ[0][0])[idx] = 0;
+            (&L.X[0][0])[idx] = 0;
+        }
+        __syncthreads();
+    }
     for (int idx = tid; idx < T * T; idx += CTH) {
         const int qq = idx / T, c = idx % T;
-        if (qq >= 1 && qq <= c && c < nJ) L.DJ[c][qq] = m[(size_t)(col0 + qq) * n + col0 + c];
+        if (qq >= 1 && qq <= c && c < nJ)
+            L.DJ[c][qq] = m[(size_t)(col0 + qq) * n + col0 + c] << (KEYED ? KB : 0);
     }
     // Bulk minimum per cell: the lexicographic minimum of the PT partial
     // pairs, or for D == 1 the single split k = (I+1)T-1.
@@ -1256,7 +1289,7 @@ __global__ __launch_bounds__(1024) void k_close_wide(const TileChain *__restrict
                     }
                 }
             }
-            L.X[c][rr] = bc;
+            L.X[c][rr] = KEYED ? (bc << KB) + (T - 1) : bc;
             L.K[c][rr] = bkk;
         }
     }
@@ -1264,7 +1297,47 @@ __global__ __launch_bounds__(1024) void k_close_wide(const TileChain *__restrict
 
     __builtin_amdgcn_s_setprio(3);
     const int wmax = (T - 1) + (nJ - 1);
-    for (int w = 0; w <= wmax; ++w) {
+    if constexpr (KEYED) {
+        for (int w = 0; w <= wmax; ++w) {
+            const int c = w - (T - 1 - r);
+            const int c_lo = w - (T - 1 - CROWS * h);
+            const int c_hi = c_lo + CROWS - 1;
+            if (c_hi >= 0 && c_lo < nJ) {  // wave-uniform
+                const int cc = min(max(c, 0), nJ - 1);
+                const uint64_t pJc = L.pJ[cc + 1];
+                int64_t best = L.X[cc][r];  // the bulk key (every lane of the row)
+#pragma unroll
+                for (int t = 0; t < CS; ++t) {  // (a) splits
+                    const int64_t v = DIr[t] + L.X[cc][t * G + g + 1] +
+                                      (int64_t)(((uint64_t)PIr[t] * pJc) << KB);
+                    best = v < best ? v : best;
+                }
+#pragma unroll
+                for (int t = 0; t < CS; ++t) {  // (b) splits
+                    const int64_t v = Xrow[t] + L.DJ[cc][t * G + g + 1] +
+                                      (int64_t)(((uint64_t)PJr[t] * pJc) << KB);
+                    best = v < best ? v : best;
+                }
+                best = dpp_key_min<0xB1>(best);   // lane ^ 1
+                best = dpp_key_min<0x4E>(best);   // lane ^ 2
+                best = dpp_key_min<0x141>(best);  // i <-> 7 - i
+                best = dpp_key_min<0x140>(best);  // i <-> 15 - i
+                if (c >= 0 && c < nJ) {
+                    const int64_t xv = best >> KB << KB;  // the final cost as a key
+                    const int kl = (int)(best - xv);
+#pragma unroll
+                    for (int t = 0; t < CS; ++t)
+                        if (t * G + g == c) Xrow[t] = xv + T + c;
+                    if (g == 0) {
+                        L.X[c][r] = xv;
+                        if (kl != T - 1) L.K[c][r] = kl < T - 1 ? row0 + kl : col0 + (kl - T);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int w = 0; w <= (KEYED ? -1 : wmax); ++w) {
         const int c = w - (T - 1 - r);
         const int c_lo = w - (T - 1 - CROWS * h);
         const int c_hi = c_lo + CROWS - 1;
@@ -1323,7 +1396,7 @@ __global__ __launch_bounds__(1024) void k_close_wide(const TileChain *__restrict
         const int rr = idx / T, c = idx % T;
         if (c < nJ) {
             const size_t o = (size_t)(row0 + rr) * n + col0 + c;
-            m[o] = L.X[c][rr];
+            m[o] = L.X[c][rr] >> (KEYED ? KB : 0);
             s[o] = L.K[c][rr];
         }
     }
@@ -1331,7 +1404,7 @@ __global__ __launch_bounds__(1024) void k_close_wide(const TileChain *__restrict
         const int c = idx / T, rr = idx % T;
         if (c < nJ) {
             const size_t o = (size_t)(col0 + c) * n + row0 + rr;
-            m[o] = L.X[c][rr];
+            m[o] = L.X[c][rr] >> (KEYED ? KB : 0);
             s[o] = -1;
         }
     }
@@ -1888,12 +1961,20 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
             else if (L.kind == TK_BULK)
                 hipLaunchKernelGGL(k_bulk_wide<false>, dim3(L.blocks), dim3(256), 0, q, chains,
                                    sg, L.nseg, m_all, p, (int64_t *)part, plan.lone ? 1 : 0);
+            else if (plan.cost_bits <= 54 && plan.pmax < 65536)
+                hipLaunchKernelGGL((k_close_wide<true, true>), dim3(L.blocks), dim3(1024),
+                                   plan.lone ? kCloseWideExtraLds : 0, q, chains, sg, L.nseg,
+                                   m_all, s_all, p, (const int64_t *)part);
+            else if (plan.cost_bits <= 54)
+                hipLaunchKernelGGL((k_close_wide<false, true>), dim3(L.blocks), dim3(1024),
+                                   plan.lone ? kCloseWideExtraLds : 0, q, chains, sg, L.nseg,
+                                   m_all, s_all, p, (const int64_t *)part);
             else if (plan.pmax < 65536)
-                hipLaunchKernelGGL(k_close_wide<true>, dim3(L.blocks), dim3(1024),
+                hipLaunchKernelGGL((k_close_wide<true, false>), dim3(L.blocks), dim3(1024),
                                    plan.lone ? kCloseWideExtraLds : 0, q, chains, sg, L.nseg,
                                    m_all, s_all, p, (const int64_t *)part);
             else
-                hipLaunchKernelGGL(k_close_wide<false>, dim3(L.blocks), dim3(1024),
+                hipLaunchKernelGGL((k_close_wide<false, false>), dim3(L.blocks), dim3(1024),
                                    plan.lone ? kCloseWideExtraLds : 0, q, chains, sg, L.nseg,
                                    m_all, s_all, p, (const int64_t *)part);
             e = hipGetLastError();

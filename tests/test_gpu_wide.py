@@ -110,6 +110,19 @@ def test_wide_costs_at_the_2_53_bound(over):
     check(p)
 
 
+@pytest.mark.parametrize("over", [0, 1])
+def test_wide_costs_at_the_2_54_bound(over):
+    # (n-1) max(p)^3 just below 2^54: the int64 closure carries keys
+    # cost * 2^7 + local split; one above: (cost, split) pairs.
+    n = 150
+    d = pmax_for(n, 54) + over
+    p = workloads.uniform_dims(n, d // 2, d, 6700 + over)
+    p[n // 4] = d
+    assert ((n - 1) * d ** 3 < (1 << 54)) == (over == 0)
+    check(p)
+    check(np.where(workloads.tie_heavy(n, 7 + over) == 1, d - 1, d).astype(np.int32))
+
+
 def test_wide_matches_wavefront_path():
     import torch
     p = workloads.uniform_dims(333, 1, pmax_for(333), 77)
