@@ -821,9 +821,13 @@ __global__ __launch_bounds__((CloseShape<64, CG_LONE>::CTH)) void k_close(
 }
 
 // Two tiles per CU (many chains: closure throughput matters); the same
-// shape serves the 32-edge tiles of batches of small chains, several per CU.
+// shape serves the 32-edge tiles of batches of small chains, several per CU:
+// held to six waves per SIMD there (at most 80 VGPRs; a few spill around the
+// sweep), which measured 3% faster on a batch of 4096 chains than the five
+// its 88 VGPRs allowed; seven spilled more and gained nothing.
 template <int T>
-__global__ __launch_bounds__((CloseShape<T, CG_PAIR>::CTH)) void k_close_pair(
+__global__ __launch_bounds__((CloseShape<T, CG_PAIR>::CTH))
+__attribute__((amdgpu_waves_per_eu(T == 32 ? 6 : 1))) void k_close_pair(
     const TileChain *__restrict__ chains, const TileSeg *__restrict__ segs, int nseg,
     int64_t *__restrict__ m_all, int32_t *__restrict__ s_all, const double *__restrict__ pd_all,
     const uint64_t *__restrict__ part_all)
