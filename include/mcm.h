@@ -72,8 +72,11 @@ typedef enum mcm_status {
  *                       (n-1) * max(p)^3 < 2^46, exact integers carried in
  *                       fp64 keys (cost * 2^kb + local split: one fma, add
  *                       and min per split); beyond that, up to the int64
- *                       limit, the same schedule on int64 costs with the
- *                       split carried apart.  Accepts every valid input.
+ *                       limit, the same schedule with the split carried
+ *                       beside the cost (the bulk in exact fp64 while
+ *                       (n-1) * max(p)^3 < 2^53, the closure on int64 keys
+ *                       while it is < 2^54, int64 pairs above).  Accepts
+ *                       every valid input.
  *   MCM_ALGO_PIPELINE   the paper's pipeline (Section IV-B, Fig. 8): the
  *                       table linearised in diagonal order, thread j folding
  *                       split j of an element one step after thread j-1, a
