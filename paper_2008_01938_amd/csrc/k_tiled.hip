@@ -339,6 +339,10 @@ struct CloseLdsPacked {
 template <int T>
 constexpr int bulk_threads() { return (T / 4) * (T / 4); }
 
+// __builtin_amdgcn_sched_barrier mask: only scalar ALU instructions may be
+// scheduled across the barrier.
+constexpr int kSchedScalarOnly = 0x0004;
+
 // 64-edge tiles: held to three waves per SIMD (at most 168 VGPRs), which
 // the kernel fits without spills; the 32-edge form runs at two.
 template <int T>
@@ -468,19 +472,63 @@ void k_bulk(const TileChain *__restrict__ chains, const TileSeg *__restrict__ se
         // for launches that share CUs with closures (batched plans).
         if (paced) set_prio(3 - (4 * rd) / rounds);
         if (more) load(kc + KC);
+        if constexpr (T == 64) {
 #pragma unroll 4
-        for (int kk = 0; kk < KC; ++kk) {
-            double av[4], bv[4];
+            for (int kk = 0; kk < KC; ++kk) {
+                double av[4], bv[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = L.As[buf][kk][ty + TW * a];
+                for (int a = 0; a < 4; ++a) av[a] = L.As[buf][kk][ty + TW * a];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) bv[b] = L.Bs[buf][kk][tx + TW * b];
-            const double pk = L.Ps[buf][kk];
+                for (int b = 0; b < 4; ++b) bv[b] = L.Bs[buf][kk][tx + TW * b];
+                const double pk = L.Ps[buf][kk];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+                for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    best[a][b] = fmin(best[a][b], fma(pj[a][b], pk, bv[b]) + av[a]);
+                    for (int b = 0; b < 4; ++b)
+                        best[a][b] = fmin(best[a][b], fma(pj[a][b], pk, bv[b]) + av[a]);
+            }
+        } else {
+            // 32-edge tiles run two waves per SIMD, too few to hide a cell's
+            // dependent fma -> add -> min when the compiler emits the cells
+            // one after another.  Here the next split's operands are read
+            // first and the row's four cells go through each stage together;
+            // scheduling barriers that let only scalar instructions cross
+            // keep that order.
+            double av[4], bv[4], pk;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = L.As[buf][0][ty + TW * a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = L.Bs[buf][0][tx + TW * b];
+            pk = L.Ps[buf][0];
+#pragma unroll 4
+            for (int kk = 0; kk < KC; ++kk) {
+                const int kn = min(kk + 1, KC - 1);  // the last split reads itself again
+                double nav[4], nbv[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) nbv[b] = L.Bs[buf][kn][tx + TW * b];
+                const double npk = L.Ps[buf][kn];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) nav[a] = L.As[buf][kn][ty + TW * a];
+                __builtin_amdgcn_sched_barrier(kSchedScalarOnly);
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    double t[4];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) t[b] = fma(pj[a][b], pk, bv[b]);
+                    __builtin_amdgcn_sched_barrier(kSchedScalarOnly);
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) t[b] = t[b] + av[a];
+                    __builtin_amdgcn_sched_barrier(kSchedScalarOnly);
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) best[a][b] = fmin(best[a][b], t[b]);
+                    __builtin_amdgcn_sched_barrier(kSchedScalarOnly);
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a) av[a] = nav[a];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) bv[b] = nbv[b];
+                pk = npk;
+            }
         }
         if (more) store(kc + KC, buf ^ 1);
         __syncthreads();
@@ -908,7 +956,7 @@ void k_bulk_mid(const TileChain *__restrict__ chains, const TileSeg *__restrict_
                 const int64_t *__restrict__ m_all, const double *__restrict__ pd_all,
                 int64_t *__restrict__ part_all, int paced)
 {
-    constexpr int T = 64, BTH = 256, TW = 16, RA = 16, RB = 4, V = 4;
+    constexpr int T = 64, TW = 16, RA = 16, RB = 4, V = 4;  // 256 threads, as k_bulk<64>
     __shared__ BulkLds<64> L;  // As, Bs: costs; Ps: p[k+1]
     const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
     const TileChain ch = chains[sg.chain];
