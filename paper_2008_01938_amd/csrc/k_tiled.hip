@@ -247,8 +247,8 @@ __global__ __launch_bounds__(NTH) void k_tri_key(const TileChain *__restrict__ c
 // ------------------------------------------------------------------------
 // Shared memory and launch shapes.
 // ------------------------------------------------------------------------
-// Closure: column stride (doubles) of its LDS tables; T + 8 is 8 (mod 16)
-// for both tile edges.
+// Paired closure: column stride (doubles) of its LDS tables; T + 8 is
+// 8 (mod 16) for both tile edges.
 template <int T>
 constexpr int cstr() { return T + 8; }
 
@@ -297,18 +297,26 @@ struct BulkLds {
 // stride of CSTR doubles.  LDS has 32 banks of 4 bytes, so a 64-bit read is
 // conflict-free when the 16 lanes served together touch distinct 8-byte
 // words modulo 16: with G = 16 those are one row group reading consecutive
-// rows of one column; with G = 8 two row groups reading adjacent columns,
-// whose starts differ by CSTR = 8 (mod 16) doubles.  Row T is a spare so
-// slot addresses never need clamping.
+// rows of one column (any stride; the full layout takes an odd one, T + 1,
+// so that the prologue's and epilogue's passes along a row, lanes a column
+// apart, are conflict-free as well); with G = 8 two row groups reading
+// adjacent columns, whose starts differ by CSTR = 8 (mod 16) doubles.  Row T
+// is a spare so slot addresses never need clamping.
+// The full layout also keeps every cell's final key (Fk), so the sweep
+// writes one value per cell and the split is read off in the epilogue; the
+// packed one records a split found by the sweep in Ks as its complement
+// (negative), resolved in the epilogue, and has no room for the keys.
 // The sweep reads column cc of the DJ table through its base offset, which a
 // lane advances as its cc grows by one (dj_next), so no per-step multiply.
 template <int T>
 struct CloseLdsFull {
-    static constexpr int CSTR = cstr<T>();
+    static constexpr int CSTR = T + 1;  // odd: a column-strided pass is conflict-free too
     double DJt[T][CSTR];   // DJt[c][q] = DJ[q][c] * 2^kb + T + q - 1 (1 <= q <= c), else 0
     double Xt[T][CSTR];    // Xt[c][q]: bulk key, then final cost * 2^kb of cell (q, c)
-    int32_t Ks[T][T + 1];  // bulk split, then final split
+    double Fk[T][CSTR];    // Fk[c][q]: final key of cell (q, c) (cost * 2^kb + k_local)
+    int32_t Ks[T][T + 1];  // bulk split
     double pJs[T + 1];     // p[col0 + q]
+    static constexpr bool kFinalKeys = true;
     __device__ double &dj(int q, int c) { return DJt[c][q]; }
     // Base of column c is c * CSTR (the same as Xt's); DJ[j+1][c] sits at
     // base + j + 1.
@@ -321,8 +329,9 @@ struct CloseLdsPacked {
     static constexpr int CSTR = cstr<T>();
     double DJp[dj_packed_size<T>()];  // column c from dj_packed_base(c): DJ[q][c] at q - 1
     double Xt[T][CSTR];
-    int32_t Ks[T][T + 1];
+    int32_t Ks[T][T + 1];  // bulk split, or ~k_local of a split the sweep found
     double pJs[T + 1];
+    static constexpr bool kFinalKeys = false;
     __device__ double &dj(int q, int c) { return DJp[dj_packed_base(c) + q - 1]; }
     // dj_packed_base(c + 1) = dj_packed_base(c) + c + ((8 - c) & 15).
     static constexpr bool kPacked = true;
@@ -831,8 +840,12 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
                     if (t * G + g == c) R.Xrow[t] = xv;
                 if (g == 0) {
                     (&L.Xt[0][0])[xo + r] = xv;
-                    const int kl = (int)fma(-base, scale, fin);
-                    if (kl != T - 1) L.Ks[r][c] = kl < T - 1 ? row0 + kl : col0 + (kl - T);
+                    if constexpr (Lds::kFinalKeys) {
+                        (&L.Fk[0][0])[xo + r] = fin;  // the split is read off at the end
+                    } else {
+                        const int kl = (int)fma(-base, scale, fin);
+                        if (kl != T - 1) L.Ks[r][c] = ~kl;  // a local split, resolved at the end
+                    }
                 }
             }
         }
@@ -844,7 +857,15 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
         if (c < nJ) {
             const size_t o = (size_t)(row0 + rr) * n + col0 + c;
             m[o] = (int64_t)(L.Xt[c][rr] * inv_scale);
-            s[o] = L.Ks[rr][c];
+            if constexpr (Lds::kFinalKeys) {
+                const double f = L.Fk[c][rr];
+                const int kl = (int)fma(-floor(f * inv_scale), scale, f);
+                s[o] = kl == T - 1 ? L.Ks[rr][c] : kl < T - 1 ? row0 + kl : col0 + (kl - T);
+            } else {
+                const int code = L.Ks[rr][c];
+                const int kl = ~code;
+                s[o] = code >= 0 ? code : kl < T - 1 ? row0 + kl : col0 + (kl - T);
+            }
         }
     }
     for (int idx = tid; idx < T * T; idx += CTH) {
