@@ -358,8 +358,24 @@ template <int T>
 __global__ __launch_bounds__(bulk_threads<T>()) __attribute__((amdgpu_waves_per_eu(T == 64 ? 3 : 2)))
 void k_bulk(const TileChain *__restrict__ chains, const TileSeg *__restrict__ segs, int nseg,
             const int64_t *__restrict__ m_all, const double *__restrict__ pd_all,
-            uint64_t *__restrict__ part_all, int paced)
+            uint64_t *__restrict__ part_all, int paced, const uint64_t *wait_word,
+            uint64_t wait_token, long long wait_ticks)
 {
+    // With a wait word, the launch's last workgroup computes nothing: its
+    // first wave waits until the word holds at least wait_token (written on
+    // another stream once the interior beside this launch is complete), so
+    // the launch ends no earlier than that interior.  The wait is bounded
+    // by wait_ticks of the constant-rate clock.
+    if (wait_word != nullptr && blockIdx.x == gridDim.x - 1) {
+        if (threadIdx.x < 64) {
+            const long long t0 = wall_clock64();
+            while (__hip_atomic_load(wait_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) <
+                       wait_token &&
+                   wall_clock64() - t0 < wait_ticks)
+                __builtin_amdgcn_s_sleep(1);
+        }
+        return;
+    }
     constexpr int BTH = bulk_threads<T>();
     constexpr int TW = T / 4;            // threads per microtile row
     constexpr int RA = BTH / KC;         // A rows staged apart per thread
@@ -1495,16 +1511,23 @@ __global__ __launch_bounds__(64) void k_delay(long long ticks)
     while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(8);
 }
 
-// Ticks of a pause (launch_delay): about 4 microseconds.
-long long delay_ticks_for_device()
+// The constant-rate clock's ticks per millisecond.
+long long clock_khz_for_device()
 {
     int device = 0, khz = 0;
     if (hipGetDevice(&device) != hipSuccess ||
         hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess ||
         khz <= 0)
         khz = 100000;
-    return (long long)khz * 4 / 1000;
+    return khz;
 }
+
+// Ticks of a pause (launch_delay): about 4 microseconds.
+long long delay_ticks_for_device() { return clock_khz_for_device() * 4 / 1000; }
+
+// Bound of an end-block launch's wait for an interior token: 2 seconds,
+// far beyond any interior (the wait ends when the token lands).
+long long wait_ticks_for_device() { return clock_khz_for_device() * 2000; }
 
 }  // namespace
 
@@ -1749,6 +1772,39 @@ int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t 
     return (int)plan.chains.size() - 1;
 }
 
+// Lone chains (two streams): where the interior of D+1 is expected to end
+// before the end blocks of D+1 (the first and last tile-diagonals), the
+// closure of D+1 does not wait for it with a stream wait (a runtime kernel
+// between two kernel boundaries, about 11 us): one extra workgroup of the
+// end-block launch waits for the interior's token instead.  In the middle
+// tile-diagonals the interior is the longer branch, and the next interior
+// waits for the end-block launch, so there the stream wait stays.  The
+// estimate: bulk at about 2.9e4 split evaluations per us on each CU it
+// holds, a closure sweep of about 80 us, and about 14 us from the
+// interior's end to its token.
+constexpr double kBulkEvalsPerUsCu = 2.9e4;
+constexpr double kSweepUs = 80.0;
+constexpr double kTokenHopUs = 14.0;
+
+bool fold_closure_wait(const TiledPlan &plan, const std::vector<ChainStep> &steps)
+{
+    if (!plan.lone || plan.serial || plan.wide || plan.T != 64 || plan.cus <= 0) return false;
+    for (const ChainStep &cs : steps) {
+        const int c = cs.chain, E = cs.D + 1, NT = plan.NT[c];
+        if (cs.D < 1 || E < 3 || E >= NT) continue;
+        const int32_t T = plan.T;
+        const double cells = diag_cells(plan.chains[c].n, NT, E, T);
+        int held = NT - E + 1;  // the closure of D holds a CU per tile
+        if (held > plan.cus - plan.cus / 4) held = plan.cus - plan.cus / 4;
+        const int free_cus = plan.cus - held;
+        const double t_int =
+            cells * ((E - 3) * T + 1) / (kBulkEvalsPerUsCu * (double)free_cus);
+        const double t_end = cells * (2.0 * T) / (kBulkEvalsPerUsCu * (double)held);
+        if (t_int + kTokenHopUs >= kSweepUs + t_end) return false;
+    }
+    return true;
+}
+
 void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
 {
     const int32_t T = plan.T;
@@ -1862,6 +1918,8 @@ void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
                      bl.PT);
         }
     }
+    if (ends.nseg && plan.last_interior >= 0 && fold_closure_wait(plan, steps))
+        ends.fold = plan.last_interior;
     if (ends.nseg) push(ends, -1);
 }
 
@@ -1996,6 +2054,10 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
     // instead of an event when the device has a signal word (a stream wait
     // on a value is a shorter hop than an event wait).
     std::vector<uint64_t> tok(plan.launches.size(), 0);
+    // Aux launches whose token a launch on the caller's stream already
+    // waited for in-kernel (TiledLaunch::fold): later launches on that
+    // stream need no stream wait for them.
+    std::vector<char> folded(plan.launches.size(), 0);
     int next_ev = 2;
     bool forked = false;
     if (aux && st == MCM_OK) {
@@ -2011,7 +2073,7 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
         const TiledLaunch &L = plan.launches[li];
         hipStream_t q = L.stream == 1 ? ss.aux : stream;
         hipError_t e = hipSuccess;
-        if (L.wait >= 0 && plan.launches[L.wait].stream != L.stream)
+        if (L.wait >= 0 && plan.launches[L.wait].stream != L.stream && !folded[L.wait])
             e = tok[L.wait] ? aux_signal_wait(q, tok[L.wait])
                             : hipStreamWaitEvent(q, rec[L.wait], 0);
         if (e != hipSuccess) {
@@ -2066,12 +2128,22 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
         } else if (L.kind == TK_BULK) {
             ProfileScope ps(KC_BULK, q, L.evals);
             const int paced = plan.lone ? 1 : 0;
+            const uint64_t *ww = nullptr;
+            uint64_t wt = 0;
+            if (L.fold >= 0 && L.stream == 0 && plan.launches[L.fold].stream == 1 &&
+                tok[L.fold] && plan.T == 64) {
+                ww = aux_signal_word();
+                wt = ww ? tok[L.fold] : 0;
+            }
             if (plan.T == 32)
                 hipLaunchKernelGGL(k_bulk<32>, dim3(L.blocks), dim3(bulk_threads<32>()), 0, q,
-                                   chains, sg, L.nseg, m_all, pd, part, paced);
+                                   chains, sg, L.nseg, m_all, pd, part, paced, nullptr,
+                                   (uint64_t)0, 0LL);
             else
-                hipLaunchKernelGGL(k_bulk<64>, dim3(L.blocks), dim3(bulk_threads<64>()), 0, q,
-                                   chains, sg, L.nseg, m_all, pd, part, paced);
+                hipLaunchKernelGGL(k_bulk<64>, dim3(L.blocks + (ww ? 1 : 0)),
+                                   dim3(bulk_threads<64>()), 0, q, chains, sg, L.nseg, m_all, pd,
+                                   part, paced, ww, wt, ww ? wait_ticks_for_device() : 0LL);
+            if (ww) folded[L.fold] = 1;
             e = hipGetLastError();
         } else if (L.kind == TK_CLOSE) {
             ProfileScope ps(KC_CLOSE, q, L.evals);

@@ -312,6 +312,15 @@ uint64_t aux_signal_write(hipStream_t aux)
     return token;
 }
 
+const uint64_t *aux_signal_word()
+{
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_streams_mu);
+    const AuxSignal &sig = g_aux_sig[device];
+    return sig.ok ? sig.word : nullptr;
+}
+
 hipError_t aux_signal_wait(hipStream_t stream, uint64_t token)
 {
     int device = 0;

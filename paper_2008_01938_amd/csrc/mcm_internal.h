@@ -111,6 +111,9 @@ struct TiledLaunch {    // one kernel launch of a tiled plan
     int stream = 0;     // 0: the caller's stream; 1: the library's aux stream
     int wait = -1;      // launch (on another stream) that must finish first
     bool record = false;  // another launch waits for this one
+    int fold = -1;      // lone end blocks: aux launch whose token an extra
+                        // workgroup of this launch waits for, so that the
+                        // closure after it on this stream needs no stream wait
 };
 
 // The library's second stream on the current device (non-blocking, default
@@ -126,6 +129,9 @@ mcm_status acquire_streams(int count, StreamSet *out);
 // holds at least `token`.
 uint64_t aux_signal_write(hipStream_t aux);
 hipError_t aux_signal_wait(hipStream_t stream, uint64_t token);
+// The current device's aux signal word (device-readable), or null before
+// the first token or on a device without one.
+const uint64_t *aux_signal_word();
 // Returns the events once every wait on them has been enqueued.
 void release_streams(StreamSet &ss);
 // Enqueue a pause of about 4 microseconds (one 64-thread workgroup waiting
