@@ -41,6 +41,7 @@
 // 2^53 and therefore exact; one fp64 min then picks the smallest cost and,
 // among equal costs, the smallest k_local -- the smallest k when k_local
 // increases with k.  A split evaluation is fma + add + min.
+#include <hip/hip_ext.h>
 #include <math.h>
 #include <string.h>
 
@@ -2069,6 +2070,11 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
         forked = st == MCM_OK;
     }
     const int cus = device_cus();
+    // Under stream capture a launch's stop event does not become a graph
+    // dependency, so captured plans record their events as markers.
+    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &capture) != hipSuccess) capture = hipStreamCaptureStatusActive;
+    const bool own_events = capture == hipStreamCaptureStatusNone;
     for (size_t li = 0; li < plan.launches.size() && st == MCM_OK; ++li) {
         const TiledLaunch &L = plan.launches[li];
         hipStream_t q = L.stream == 1 ? ss.aux : stream;
@@ -2135,10 +2141,25 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
                 ww = aux_signal_word();
                 wt = ww ? tok[L.fold] : 0;
             }
-            if (plan.T == 32)
+            // End blocks, which the next interior waits for: the event is
+            // the launch's own completion, so no marker packet sits between
+            // it and the closure after it on this stream (measured about
+            // 7 us on that path at the first and last tile-diagonals).
+            const bool own_event = own_events && aux && L.record && L.stream == 0;
+            if (own_event) rec[li] = ss.events[next_ev++];
+            if (plan.T == 32 && own_event)
+                hipExtLaunchKernelGGL(k_bulk<32>, dim3(L.blocks), dim3(bulk_threads<32>()), 0, q,
+                                      nullptr, rec[li], 0u, chains, sg, L.nseg, m_all, pd, part,
+                                      paced, (const uint64_t *)nullptr, (uint64_t)0, 0LL);
+            else if (plan.T == 32)
                 hipLaunchKernelGGL(k_bulk<32>, dim3(L.blocks), dim3(bulk_threads<32>()), 0, q,
                                    chains, sg, L.nseg, m_all, pd, part, paced, nullptr,
                                    (uint64_t)0, 0LL);
+            else if (own_event)
+                hipExtLaunchKernelGGL(k_bulk<64>, dim3(L.blocks + (ww ? 1 : 0)),
+                                      dim3(bulk_threads<64>()), 0, q, nullptr, rec[li], 0u, chains,
+                                      sg, L.nseg, m_all, pd, part, paced, ww, wt,
+                                      ww ? wait_ticks_for_device() : 0LL);
             else
                 hipLaunchKernelGGL(k_bulk<64>, dim3(L.blocks + (ww ? 1 : 0)),
                                    dim3(bulk_threads<64>()), 0, q, chains, sg, L.nseg, m_all, pd,
@@ -2176,7 +2197,7 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
         }
         if (e == hipSuccess && L.record && aux) {
             if (L.stream == 1 && !events_only && !aux_stream) tok[li] = aux_signal_write(ss.aux);
-            if (!tok[li]) {
+            if (!tok[li] && !rec[li]) {
                 rec[li] = ss.events[next_ev++];
                 e = hipEventRecord(rec[li], q);
             }
