@@ -353,6 +353,23 @@ constexpr int bulk_threads() { return (T / 4) * (T / 4); }
 // scheduled across the barrier.
 constexpr int kSchedScalarOnly = 0x0004;
 
+// With a wait word, a bulk launch's last workgroup computes nothing: its
+// first wave waits until the word holds at least `token` (written on
+// another stream once the interior beside the launch is complete), so the
+// launch ends no earlier than that interior.  The wait is bounded by
+// `ticks` of the constant-rate clock.  True for that workgroup.
+__device__ __forceinline__ bool bulk_waiter(const uint64_t *word, uint64_t token, long long ticks)
+{
+    if (word == nullptr || blockIdx.x != gridDim.x - 1) return false;
+    if (threadIdx.x < 64) {
+        const long long t0 = wall_clock64();
+        while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) < token &&
+               wall_clock64() - t0 < ticks)
+            __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+}
+
 // 64-edge tiles: held to three waves per SIMD (at most 168 VGPRs), which
 // the kernel fits without spills; the 32-edge form runs at two.
 template <int T>
@@ -362,21 +379,7 @@ void k_bulk(const TileChain *__restrict__ chains, const TileSeg *__restrict__ se
             uint64_t *__restrict__ part_all, int paced, const uint64_t *wait_word,
             uint64_t wait_token, long long wait_ticks)
 {
-    // With a wait word, the launch's last workgroup computes nothing: its
-    // first wave waits until the word holds at least wait_token (written on
-    // another stream once the interior beside this launch is complete), so
-    // the launch ends no earlier than that interior.  The wait is bounded
-    // by wait_ticks of the constant-rate clock.
-    if (wait_word != nullptr && blockIdx.x == gridDim.x - 1) {
-        if (threadIdx.x < 64) {
-            const long long t0 = wall_clock64();
-            while (__hip_atomic_load(wait_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) <
-                       wait_token &&
-                   wall_clock64() - t0 < wait_ticks)
-                __builtin_amdgcn_s_sleep(1);
-        }
-        return;
-    }
+    if (bulk_waiter(wait_word, wait_token, wait_ticks)) return;
     constexpr int BTH = bulk_threads<T>();
     constexpr int TW = T / 4;            // threads per microtile row
     constexpr int RA = BTH / KC;         // A rows staged apart per thread
@@ -992,8 +995,10 @@ __device__ __forceinline__ double cost53(u32x2 x)
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 void k_bulk_mid(const TileChain *__restrict__ chains, const TileSeg *__restrict__ segs, int nseg,
                 const int64_t *__restrict__ m_all, const double *__restrict__ pd_all,
-                int64_t *__restrict__ part_all, int paced)
+                int64_t *__restrict__ part_all, int paced, const uint64_t *wait_word,
+                uint64_t wait_token, long long wait_ticks)
 {
+    if (bulk_waiter(wait_word, wait_token, wait_ticks)) return;
     constexpr int T = 64, TW = 16, RA = 16, RB = 4, V = 4;  // 256 threads, as k_bulk<64>
     __shared__ BulkLds<64> L;  // As, Bs: costs; Ps: p[k+1]
     const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
@@ -1125,8 +1130,11 @@ __global__ __launch_bounds__(256) void k_bulk_wide(const TileChain *__restrict__
                                                   const TileSeg *__restrict__ segs, int nseg,
                                                   const int64_t *__restrict__ m_all,
                                                   const int32_t *__restrict__ p_all,
-                                                  int64_t *__restrict__ part_all, int paced)
+                                                  int64_t *__restrict__ part_all, int paced,
+                                                  const uint64_t *wait_word, uint64_t wait_token,
+                                                  long long wait_ticks)
 {
+    if (bulk_waiter(wait_word, wait_token, wait_ticks)) return;
     constexpr int T = WT, TW = 16, RA = 16, RB = 4, V = 4;
     __shared__ BulkLdsWide L;
     const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
@@ -1781,15 +1789,19 @@ int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t 
 // tile-diagonals the interior is the longer branch, and the next interior
 // waits for the end-block launch, so there the stream wait stays.  The
 // estimate: bulk at about 2.9e4 split evaluations per us on each CU it
-// holds, a closure sweep of about 80 us, and about 14 us from the
-// interior's end to its token.
+// holds, a closure sweep of about 80 us (exact int64 kernels: 1.6e4 and
+// 130 us), and about 14 us from the interior's end to its token.
 constexpr double kBulkEvalsPerUsCu = 2.9e4;
 constexpr double kSweepUs = 80.0;
+constexpr double kWideBulkEvalsPerUsCu = 1.6e4;
+constexpr double kWideSweepUs = 130.0;
 constexpr double kTokenHopUs = 14.0;
 
 bool fold_closure_wait(const TiledPlan &plan, const std::vector<ChainStep> &steps)
 {
-    if (!plan.lone || plan.serial || plan.wide || plan.T != 64 || plan.cus <= 0) return false;
+    if (!plan.lone || plan.serial || plan.T != 64 || plan.cus <= 0) return false;
+    const double rate = plan.wide ? kWideBulkEvalsPerUsCu : kBulkEvalsPerUsCu;
+    const double sweep = plan.wide ? kWideSweepUs : kSweepUs;
     for (const ChainStep &cs : steps) {
         const int c = cs.chain, E = cs.D + 1, NT = plan.NT[c];
         if (cs.D < 1 || E < 3 || E >= NT) continue;
@@ -1798,10 +1810,9 @@ bool fold_closure_wait(const TiledPlan &plan, const std::vector<ChainStep> &step
         int held = NT - E + 1;  // the closure of D holds a CU per tile
         if (held > plan.cus - plan.cus / 4) held = plan.cus - plan.cus / 4;
         const int free_cus = plan.cus - held;
-        const double t_int =
-            cells * ((E - 3) * T + 1) / (kBulkEvalsPerUsCu * (double)free_cus);
-        const double t_end = cells * (2.0 * T) / (kBulkEvalsPerUsCu * (double)held);
-        if (t_int + kTokenHopUs >= kSweepUs + t_end) return false;
+        const double t_int = cells * ((E - 3) * T + 1) / (rate * (double)free_cus);
+        const double t_end = cells * (2.0 * T) / (rate * (double)held);
+        if (t_int + kTokenHopUs >= sweep + t_end) return false;
     }
     return true;
 }
@@ -2027,6 +2038,21 @@ mcm_status run_tiled_plan(const TiledPlan &plan, const int32_t *p, const double 
     return st;
 }
 
+namespace {
+// A launch whose completion `stop` (if not null) records: the event is the
+// dispatch's own completion, with no marker packet after it.
+template <typename K, typename... A>
+void launch_with_stop(K kernel, unsigned blocks, unsigned threads, hipStream_t q, hipEvent_t stop,
+                      A... args)
+{
+    if (stop)
+        hipExtLaunchKernelGGL(kernel, dim3(blocks), dim3(threads), 0, q, nullptr, stop, 0u,
+                              args...);
+    else
+        hipLaunchKernelGGL(kernel, dim3(blocks), dim3(threads), 0, q, args...);
+}
+}  // namespace
+
 mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const TileSeg *segs,
                            const int32_t *p, const double *pd, int64_t *m_all, int32_t *s_all,
                            uint64_t *part_ext, hipStream_t stream, const ObstWeights *ob,
@@ -2087,6 +2113,27 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
             break;
         }
         const TileSeg *sg = segs + L.seg_begin;
+        // Bulk launches.  End blocks (fold): one extra workgroup waits for
+        // the interior's token.  End blocks the next interior waits for:
+        // the event is the launch's own completion, so no marker packet
+        // sits between it and the closure after it on this stream (about
+        // 7 us on that path at the first and last tile-diagonals).
+        const uint64_t *ww = nullptr;
+        uint64_t wt = 0;
+        hipEvent_t stop = nullptr;
+        if (L.kind == TK_BULK) {
+            if (L.fold >= 0 && L.stream == 0 && plan.launches[L.fold].stream == 1 &&
+                tok[L.fold] && plan.T == 64) {
+                ww = aux_signal_word();
+                wt = ww ? tok[L.fold] : 0;
+            }
+            if (own_events && aux && L.record && L.stream == 0) {
+                rec[li] = ss.events[next_ev++];
+                stop = rec[li];
+            }
+        }
+        const long long wticks = ww ? wait_ticks_for_device() : 0LL;
+        const unsigned bblocks = (unsigned)L.blocks + (ww ? 1u : 0u);
         if (plan.wide) {
             ProfileScope ps(L.kind == TK_TRI ? KC_SETUP : L.kind == TK_BULK ? KC_BULK : KC_CLOSE,
                             q, L.evals);
@@ -2094,14 +2141,14 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
                 hipLaunchKernelGGL((k_tri<64, false>), dim3(L.blocks), dim3(NTH), 0, q, chains,
                                    sg, L.nseg, p, m_all, s_all, nullptr, nullptr, nullptr);
             else if (L.kind == TK_BULK && plan.cost_bits <= 53)
-                hipLaunchKernelGGL(k_bulk_mid, dim3(L.blocks), dim3(256), 0, q, chains, sg,
-                                   L.nseg, m_all, pd, (int64_t *)part, plan.lone ? 1 : 0);
+                launch_with_stop(k_bulk_mid, bblocks, 256, q, stop, chains, sg, L.nseg, m_all, pd,
+                                 (int64_t *)part, plan.lone ? 1 : 0, ww, wt, wticks);
             else if (L.kind == TK_BULK && plan.pmax < 65536)
-                hipLaunchKernelGGL(k_bulk_wide<true>, dim3(L.blocks), dim3(256), 0, q, chains, sg,
-                                   L.nseg, m_all, p, (int64_t *)part, plan.lone ? 1 : 0);
+                launch_with_stop(k_bulk_wide<true>, bblocks, 256, q, stop, chains, sg, L.nseg,
+                                 m_all, p, (int64_t *)part, plan.lone ? 1 : 0, ww, wt, wticks);
             else if (L.kind == TK_BULK)
-                hipLaunchKernelGGL(k_bulk_wide<false>, dim3(L.blocks), dim3(256), 0, q, chains,
-                                   sg, L.nseg, m_all, p, (int64_t *)part, plan.lone ? 1 : 0);
+                launch_with_stop(k_bulk_wide<false>, bblocks, 256, q, stop, chains, sg, L.nseg,
+                                 m_all, p, (int64_t *)part, plan.lone ? 1 : 0, ww, wt, wticks);
             else if (plan.cost_bits <= 54 && plan.pmax < 65536)
                 hipLaunchKernelGGL((k_close_wide<true, true>), dim3(L.blocks), dim3(1024),
                                    plan.lone ? kCloseWideExtraLds : 0, q, chains, sg, L.nseg,
@@ -2134,37 +2181,12 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
         } else if (L.kind == TK_BULK) {
             ProfileScope ps(KC_BULK, q, L.evals);
             const int paced = plan.lone ? 1 : 0;
-            const uint64_t *ww = nullptr;
-            uint64_t wt = 0;
-            if (L.fold >= 0 && L.stream == 0 && plan.launches[L.fold].stream == 1 &&
-                tok[L.fold] && plan.T == 64) {
-                ww = aux_signal_word();
-                wt = ww ? tok[L.fold] : 0;
-            }
-            // End blocks, which the next interior waits for: the event is
-            // the launch's own completion, so no marker packet sits between
-            // it and the closure after it on this stream (measured about
-            // 7 us on that path at the first and last tile-diagonals).
-            const bool own_event = own_events && aux && L.record && L.stream == 0;
-            if (own_event) rec[li] = ss.events[next_ev++];
-            if (plan.T == 32 && own_event)
-                hipExtLaunchKernelGGL(k_bulk<32>, dim3(L.blocks), dim3(bulk_threads<32>()), 0, q,
-                                      nullptr, rec[li], 0u, chains, sg, L.nseg, m_all, pd, part,
-                                      paced, (const uint64_t *)nullptr, (uint64_t)0, 0LL);
-            else if (plan.T == 32)
-                hipLaunchKernelGGL(k_bulk<32>, dim3(L.blocks), dim3(bulk_threads<32>()), 0, q,
-                                   chains, sg, L.nseg, m_all, pd, part, paced, nullptr,
-                                   (uint64_t)0, 0LL);
-            else if (own_event)
-                hipExtLaunchKernelGGL(k_bulk<64>, dim3(L.blocks + (ww ? 1 : 0)),
-                                      dim3(bulk_threads<64>()), 0, q, nullptr, rec[li], 0u, chains,
-                                      sg, L.nseg, m_all, pd, part, paced, ww, wt,
-                                      ww ? wait_ticks_for_device() : 0LL);
+            if (plan.T == 32)
+                launch_with_stop(k_bulk<32>, bblocks, bulk_threads<32>(), q, stop, chains, sg,
+                                 L.nseg, m_all, pd, part, paced, ww, wt, wticks);
             else
-                hipLaunchKernelGGL(k_bulk<64>, dim3(L.blocks + (ww ? 1 : 0)),
-                                   dim3(bulk_threads<64>()), 0, q, chains, sg, L.nseg, m_all, pd,
-                                   part, paced, ww, wt, ww ? wait_ticks_for_device() : 0LL);
-            if (ww) folded[L.fold] = 1;
+                launch_with_stop(k_bulk<64>, bblocks, bulk_threads<64>(), q, stop, chains, sg,
+                                 L.nseg, m_all, pd, part, paced, ww, wt, wticks);
             e = hipGetLastError();
         } else if (L.kind == TK_CLOSE) {
             ProfileScope ps(KC_CLOSE, q, L.evals);
@@ -2195,6 +2217,7 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
                                    m_all, s_all, pd, part);
             e = hipGetLastError();
         }
+        if (e == hipSuccess && ww) folded[L.fold] = 1;
         if (e == hipSuccess && L.record && aux) {
             if (L.stream == 1 && !events_only && !aux_stream) tok[li] = aux_signal_write(ss.aux);
             if (!tok[li] && !rec[li]) {
