@@ -1592,6 +1592,34 @@ namespace {
 // and 128 3% slower.
 constexpr int32_t kCloseSplits = 192;
 
+// Lone chains (two streams): where the interior of E is expected to end
+// before the end blocks of E (the first and last tile-diagonals), the
+// closure of E does not wait for it with a stream wait (a runtime kernel
+// between two kernel boundaries, about 11 us): one extra workgroup of the
+// end-block launch waits for the interior's token instead, and the end
+// blocks' chunks fit the whole device (the interior no longer holds CUs).
+// In the middle tile-diagonals the interior is the longer branch, and the
+// next interior waits for the end-block launch, so there the stream wait
+// stays.  The estimate: bulk at about 2.9e4 split evaluations per us on each
+// CU it holds, a closure sweep of about 80 us (exact int64 kernels: 1.6e4
+// and 130 us), and about 14 us from the interior's end to its token.
+constexpr double kBulkEvalsPerUsCu = 2.9e4;
+constexpr double kSweepUs = 80.0;
+constexpr double kWideBulkEvalsPerUsCu = 1.6e4;
+constexpr double kWideSweepUs = 130.0;
+constexpr double kTokenHopUs = 14.0;
+
+bool interior_ends_first(int32_t T, int32_t tiles, int32_t E, int held, int free_cus, bool wide)
+{
+    if (E < 3 || held <= 0 || free_cus <= 0) return false;
+    const double rate = wide ? kWideBulkEvalsPerUsCu : kBulkEvalsPerUsCu;
+    const double sweep = wide ? kWideSweepUs : kSweepUs;
+    const double cells = (double)tiles * T * T;
+    const double t_int = cells * ((E - 3) * T + 1) / (rate * (double)free_cus);
+    const double t_end = cells * (2.0 * T) / (rate * (double)held);
+    return t_int + kTokenHopUs < sweep + t_end;
+}
+
 double wave_cost(int64_t units, int32_t ks, int64_t slots)
 {
     const int64_t waves = (units + slots - 1) / slots;
@@ -1601,7 +1629,7 @@ double wave_cost(int64_t units, int32_t ks, int64_t slots)
 }  // namespace
 
 BulkLayout bulk_layout(int32_t T, int32_t NT, int32_t E, int32_t kb, bool lone, int cus,
-                       int slots_per_cu, bool serial)
+                       int slots_per_cu, bool serial, bool wide)
 {
     BulkLayout bl{};
     if (E < 2 || E >= NT) return bl;
@@ -1620,7 +1648,11 @@ BulkLayout bulk_layout(int32_t T, int32_t NT, int32_t E, int32_t kb, bool lone, 
         if (held > cus - cus / 4) held = cus - cus / 4;
         slots_int = (int64_t)slots_per_cu * (cus - held);
         slots_end = (int64_t)slots_per_cu * held;
+        bl.fold = T == 64 && interior_ends_first(T, tiles, E, (int)held, (int)(cus - held), wide);
     }
+    // The end blocks' slots: the closure's CUs, or the whole device once the
+    // interior is expected to be done (fold).
+    const int64_t slots_endblk = bl.fold ? (int64_t)slots_per_cu * cus : slots_end;
     // End blocks: E == 2 has a single range of T+1 splits, E >= 3 two of T.
     const int32_t end_len = E == 2 ? T + 1 : T;
     bl.n_end_ranges = E == 2 ? 1 : 2;
@@ -1629,7 +1661,7 @@ BulkLayout bulk_layout(int32_t T, int32_t NT, int32_t E, int32_t kb, bool lone, 
         double best = 0.0;
         for (int32_t ks = KC; ks <= end_len + KC - 1; ks += KC) {
             const int32_t nch = (end_len + ks - 1) / ks;
-            const double c = wave_cost((int64_t)tiles * bl.n_end_ranges * nch, ks, slots_end);
+            const double c = wave_cost((int64_t)tiles * bl.n_end_ranges * nch, ks, slots_endblk);
             if (ks == KC || c < best) {
                 best = c;
                 end_ks = ks;
@@ -1781,40 +1813,19 @@ int plan_add_chain(TiledPlan &plan, const ChainInfo &ci, int64_t m_off, int64_t 
     return (int)plan.chains.size() - 1;
 }
 
-// Lone chains (two streams): where the interior of D+1 is expected to end
-// before the end blocks of D+1 (the first and last tile-diagonals), the
-// closure of D+1 does not wait for it with a stream wait (a runtime kernel
-// between two kernel boundaries, about 11 us): one extra workgroup of the
-// end-block launch waits for the interior's token instead.  In the middle
-// tile-diagonals the interior is the longer branch, and the next interior
-// waits for the end-block launch, so there the stream wait stays.  The
-// estimate: bulk at about 2.9e4 split evaluations per us on each CU it
-// holds, a closure sweep of about 80 us (exact int64 kernels: 1.6e4 and
-// 130 us), and about 14 us from the interior's end to its token.
-constexpr double kBulkEvalsPerUsCu = 2.9e4;
-constexpr double kSweepUs = 80.0;
-constexpr double kWideBulkEvalsPerUsCu = 1.6e4;
-constexpr double kWideSweepUs = 130.0;
-constexpr double kTokenHopUs = 14.0;
-
+// The end blocks carry the closure's wait for the interior beside them
+// where the layout expects the interior to end first (BulkLayout::fold).
 bool fold_closure_wait(const TiledPlan &plan, const std::vector<ChainStep> &steps)
 {
-    if (!plan.lone || plan.serial || plan.T != 64 || plan.cus <= 0) return false;
-    const double rate = plan.wide ? kWideBulkEvalsPerUsCu : kBulkEvalsPerUsCu;
-    const double sweep = plan.wide ? kWideSweepUs : kSweepUs;
+    if (!plan.lone || plan.serial || plan.T != 64) return false;
+    bool any = false;
     for (const ChainStep &cs : steps) {
-        const int c = cs.chain, E = cs.D + 1, NT = plan.NT[c];
+        const int E = cs.D + 1, NT = plan.NT[cs.chain];
         if (cs.D < 1 || E < 3 || E >= NT) continue;
-        const int32_t T = plan.T;
-        const double cells = diag_cells(plan.chains[c].n, NT, E, T);
-        int held = NT - E + 1;  // the closure of D holds a CU per tile
-        if (held > plan.cus - plan.cus / 4) held = plan.cus - plan.cus / 4;
-        const int free_cus = plan.cus - held;
-        const double t_int = cells * ((E - 3) * T + 1) / (rate * (double)free_cus);
-        const double t_end = cells * (2.0 * T) / (rate * (double)held);
-        if (t_int + kTokenHopUs >= sweep + t_end) return false;
+        if (!cs.next.fold) return false;
+        any = true;
     }
-    return true;
+    return any;
 }
 
 void plan_add_iteration(TiledPlan &plan, const std::vector<ChainStep> &steps)
@@ -1959,7 +1970,7 @@ void plan_lockstep(TiledPlan &plan, const std::vector<int> &ids)
                     v[E] = bulk_layout_chunks(plan.T, NT, E, kb, nch);
                 } else {
                     v[E] = bulk_layout(plan.T, NT, E, kb, plan.lone, plan.cus,
-                                       plan.slots_per_cu, plan.serial);
+                                       plan.slots_per_cu, plan.serial, plan.wide);
                 }
             }
         }

@@ -156,6 +156,9 @@ struct BulkLayout {
     int32_t n_end_ranges = 0;              // 1 (E == 2) or 2
     int32_t PT = 0;                        // partial slots per tile
     size_t elems = 0;                      // partial-minima elements (uint64) of all tiles
+    bool fold = false;  // lone, two streams: the interior is expected to end before
+                        // the end blocks, which then fit the whole device and carry
+                        // the closure's wait for the interior
 };
 
 // pd[t] = p[t] for t < count, on the device.
@@ -304,9 +307,9 @@ int32_t tiled_nt(int32_t n, int32_t T = 64);
 void plan_make_serial(TiledPlan &plan);
 // lone: cus / slots_per_cu describe the device (TiledPlan); else ignored.
 // T: tile edge (64 or 32).  serial: the launches run alone on the device
-// (every CU free).
+// (every CU free).  wide: the exact int64 kernels (another rate estimate).
 BulkLayout bulk_layout(int32_t T, int32_t NT, int32_t E, int32_t kb, bool lone, int cus = 0,
-                       int slots_per_cu = 0, bool serial = false);
+                       int slots_per_cu = 0, bool serial = false, bool wide = false);
 // Interior cut into `nch` chunks per tile (clamped to [1, kMaxChunks] and
 // to chunks of at least 64 splits), end blocks in chunks of 64 splits.
 BulkLayout bulk_layout_chunks(int32_t T, int32_t NT, int32_t E, int32_t kb, int32_t nch);
