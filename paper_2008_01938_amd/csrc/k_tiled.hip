@@ -18,9 +18,10 @@
 // [(I+1)T-1, (I+2)T-2] and [(J-1)T, JT-1], read tiles of tile-diagonal
 // D-1; the interior between them reads only tiles of diagonals <= D-2.
 //
-// k_tri_key fills the diagonal tiles (all their splits stay inside the
-// tile) on fp64 keys; k_tri<true> does it in int64 with the optimal-BST
-// weights.
+// k_tri_rows fills the diagonal tiles (all their splits stay inside the
+// tile) on fp64 keys in row groups, as the closure sweeps (k_tri_key, lanes
+// per cell and a shuffle tree, for many 64-edge tiles at once); k_tri<true>
+// does it in int64 with the optimal-BST weights.
 // k_bulk: a min-plus-like reduction over a chunk of a tile's bulk range.
 //         The A panel (rows of I, columns k) and the B panel (rows k+1,
 //         columns of J) are staged through LDS; each thread keeps a 4 x 4
@@ -894,6 +895,97 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
             const size_t o = (size_t)(col0 + c) * n + row0 + rr;
             m[o] = (int64_t)(L.Xt[c][rr] * inv_scale);
             s[o] = -1;
+        }
+    }
+}
+
+// Diagonal tiles in row groups (fp64 keys): G lanes own local row r; at
+// step d (local diagonal, 1 .. nI-1) the group finalises cell (r, r + d)
+// from the splits k in [r, r + d - 1]: X[r][k] (its own row, final at an
+// earlier step, kept in registers with k added: lane g holds k = t*G + g in
+// slot t) + X[k+1][c] (column c, rows below, from LDS) + p_r p_{k+1}
+// p_{c+1}.  Slots whose left cell is not final (k >= c) or not a cell
+// (k < r) hold 2^62 and lose.  One barrier per step publishes the new
+// cells; the split is read off each cell's final key at the end.  Every
+// split is evaluated once per slot, as in the closure, instead of lanes per
+// cell and a shuffle tree (k_tri_key's form, kept for launches of many
+// 64-edge tiles).
+template <int T, int G>
+__global__ __launch_bounds__(T * G) void k_tri_rows(const TileChain *__restrict__ chains,
+                                                    const TileSeg *__restrict__ segs, int nseg,
+                                                    const double *__restrict__ pd_all,
+                                                    int64_t *__restrict__ m_all,
+                                                    int32_t *__restrict__ s_all)
+{
+    constexpr int CTH = T * G, CS = T / G, ROWS = 64 / G;  // rows per wave
+    // Column stride: odd for 16-lane rows (any stride serves one row group's
+    // 16-lane LDS pass; odd also the epilogue's); 8 (mod 16) for 8-lane rows,
+    // whose two row groups per pass read adjacent columns.
+    constexpr int TS = G == 16 ? T + 1 : T + 8;
+    __shared__ double Xt[T][TS];  // Xt[c][q]: final cost * 2^kb of cell (q, c)
+    __shared__ double Fk[T][TS];  // Fk[c][q]: its final key (cost * 2^kb + k_local)
+    __shared__ double ps[T + 1];
+    const int tid = threadIdx.x;
+    const TileSeg sg = segs[find_seg(segs, nseg, blockIdx.x)];
+    const TileChain ch = chains[sg.chain];
+    const int32_t n = ch.n;
+    const double *__restrict__ pd = pd_all + ch.pd_off;
+    int64_t *__restrict__ m = m_all + ch.m_off;
+    int32_t *__restrict__ s = s_all + ch.s_off;
+    const double scale = ldexp(1.0, ch.kb), inv_scale = ldexp(1.0, -ch.kb);
+    const int base = (blockIdx.x - sg.first) * T;
+    const int nI = min(T, n - base);
+    const int r = tid / G, g = tid % G;
+    const int h = __builtin_amdgcn_readfirstlane(tid / 64);
+
+    for (int q = tid; q <= T; q += CTH) ps[q] = q <= nI ? pd[base + min(q, nI)] : 0.0;
+    for (int idx = tid; idx < T * TS; idx += CTH) (&Xt[0][0])[idx] = 0.0;
+    __syncthreads();
+    // Own-row operands: slot t of lane g is split k = t*G + g.
+    double Xk[CS], PR[CS];
+    const double pr = ps[r] * scale;
+#pragma unroll
+    for (int t = 0; t < CS; ++t) {
+        const int k = t * G + g;
+        Xk[t] = k == r ? (double)k : kPad;  // cell (r, r) costs 0
+        PR[t] = pr * ps[min(k + 1, T)];
+    }
+
+    for (int d = 1; d < nI; ++d) {
+        if (ROWS * h + d < nI) {  // wave-uniform: some row of the wave is active
+            const int c = min(r + d, nI - 1);
+            const double pc = ps[c + 1];
+            const double *__restrict__ col = &Xt[c][0];
+            double v[CS];
+#pragma unroll
+            for (int t = 0; t < CS; ++t) v[t] = fma(PR[t], pc, col[t * G + g + 1]) + Xk[t];
+            const double best = min_group<G>(range_min<0, CS>(v));
+            const double cost = floor(best * inv_scale);
+            const double xv = cost * scale;
+            if (r + d < nI) {
+#pragma unroll
+                for (int t = 0; t < CS; ++t)
+                    if (t * G + g == c) Xk[t] = xv + (double)c;
+                if (g == 0) {
+                    Xt[c][r] = xv;
+                    Fk[c][r] = best;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    for (int idx = tid; idx < T * T; idx += CTH) {
+        const int rr = idx / T, cc = idx % T;
+        if (rr < nI && cc < nI) {
+            const size_t o = (size_t)(base + rr) * n + base + cc;
+            m[o] = (int64_t)((rr <= cc ? Xt[cc][rr] : Xt[rr][cc]) * inv_scale);
+            if (rr < cc) {
+                const double f = Fk[cc][rr];
+                s[o] = base + (int32_t)fma(-floor(f * inv_scale), scale, f);
+            } else {
+                s[o] = -1;
+            }
         }
     }
 }
@@ -2183,11 +2275,17 @@ mcm_status exec_tiled_plan(const TiledPlan &plan, const TileChain *chains, const
                 hipLaunchKernelGGL((k_tri<64, true>), dim3(L.blocks), dim3(NTH), 0, q, chains, sg,
                                    L.nseg, p, m_all, s_all, ob->hi, ob->lo, ob->q);
             else if (plan.T == 32)
-                hipLaunchKernelGGL(k_tri_key<32>, dim3(L.blocks), dim3(NTH), 0, q, chains, sg,
-                                   L.nseg, pd, m_all, s_all);
-            else
+                hipLaunchKernelGGL((k_tri_rows<32, 8>), dim3(L.blocks), dim3(32 * 8), 0, q,
+                                   chains, sg, L.nseg, pd, m_all, s_all);
+            else if (!plan.lone && L.blocks > cus)
+                // Many 64-edge tiles: the 1024-thread row-group form fits one
+                // or two per CU, the 256-thread form more (measured faster
+                // on a batch of 4096 chains).
                 hipLaunchKernelGGL(k_tri_key<64>, dim3(L.blocks), dim3(NTH), 0, q, chains, sg,
                                    L.nseg, pd, m_all, s_all);
+            else
+                hipLaunchKernelGGL((k_tri_rows<64, 16>), dim3(L.blocks), dim3(64 * 16), 0, q,
+                                   chains, sg, L.nseg, pd, m_all, s_all);
             e = hipGetLastError();
         } else if (L.kind == TK_BULK) {
             ProfileScope ps(KC_BULK, q, L.evals);
