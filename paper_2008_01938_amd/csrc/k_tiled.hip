@@ -1776,11 +1776,11 @@ BulkLayout bulk_layout(int32_t T, int32_t NT, int32_t E, int32_t kb, bool lone, 
             // Chunks per tile (at most 32 partial slots) that minimise the
             // estimated duration on the interior's slots.
             double best = 0.0;
-            // Where the interior has slack (fold), chunks of at least 48
+            // Where the interior has slack (fold), chunks of at least 192
             // splits: a short interior cut finer than that ran slower (and
             // left more partial minima for the closure to merge).
             int32_t most = kMaxChunks;
-            if (bl.fold && L / 48 < most) most = L / 48 > 1 ? L / 48 : 1;
+            if (bl.fold && L / 192 < most) most = L / 192 > 1 ? L / 192 : 1;
             for (int32_t want = 1; want <= most && (want - 1) * KC < L; ++want) {
                 int32_t k = (L + want - 1) / want;
                 k = (k + KC - 1) / KC * KC;
