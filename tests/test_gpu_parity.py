@@ -96,6 +96,19 @@ def test_config_n2048(algo):
     assert_tables_equal(workloads.single_n2048(), algo)
 
 
+# Ragged mid sizes on the tiled path, whole tables: schedules in which the
+# closure's wait for the interior sits in the end-block launch at every
+# tile-diagonal (n up to about 4096) or only at the first and last ones,
+# interiors chunked by their slack, last tiles 1 or 57 columns wide.
+@pytest.mark.parametrize("n", [1025, 3001, 4097])
+def test_ragged_mid_sizes_whole_table(n):
+    assert_tables_equal(workloads.uniform_dims(n, 1, 1024, 9500 + n), "tiled")
+
+
+def test_tie_heavy_n3001_whole_table():
+    assert_tables_equal(workloads.tie_heavy(3001, 77), "tiled")
+
+
 @pytest.mark.parametrize("algo", ["wavefront", "tiled", "auto"])
 def test_large_values(algo):
     # Costs near 2^62: beyond the fp64 keys' exact range; the tiled path
