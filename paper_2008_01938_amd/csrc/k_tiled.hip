@@ -677,6 +677,21 @@ __device__ __forceinline__ double close_step_at(int t0, const CloseRegs<T, G> &R
     return close_step<T, G, T0>(R, L, xo, djb, g, pJc);
 }
 
+// Cells a thread of a 32-edge paired closure moves between global memory
+// and the packed LDS tables (column stride 8 mod 16 doubles, so lanes a
+// column apart hit 2 banks in 16): the tile in 8 x 8 blocks of 64 flat
+// indices, each 16 consecutive indices 2 columns x 8 rows (16 distinct
+// banks), a wave's 64 covering 8 consecutive columns of 8 rows (64-byte
+// runs in global memory).  Thread tid's u-th cell (index tid + CTH*u, with
+// CTH / 64 == T / 8) is (rr0 + 8u, cc0).
+template <int T>
+__device__ __forceinline__ void blocked_cell(int tid, int &rr0, int &cc0)
+{
+    const int b = tid >> 6, l = tid & 63, j = l & 15;
+    rr0 = ((b / (T / 8)) << 3) + (j >> 1);
+    cc0 = ((b % (T / 8)) << 3) + ((l >> 4) << 1) + (j & 1);
+}
+
 // OB: the optimal-BST weights (pd_all then holds zeros, so every product
 // term vanishes): a cell gains W(i, j) = ob_hi[j] - ob_lo[i] once its
 // minimum is known.  pJs then carries ob_hi of the tile's columns.
@@ -710,6 +725,13 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
     const uint64_t kmask = (((uint64_t)1) << kbits) - 1;
 
     const int r = tid / G, g = tid % G;
+    // 32-edge packed tables: prologue and epilogue in blocked cells (the
+    // 64-edge ones keep row-major cells: the map cost them registers that
+    // two workgroups per CU cannot spare).
+    constexpr bool BLK = Lds::kPacked && T == 32;
+    static_assert(!BLK || CTH / 64 == T / 8, "blocked cells");
+    int rr0 = 0, cc0 = 0;
+    if constexpr (BLK) blocked_cell<T>(tid, rr0, cc0);
     const int h = __builtin_amdgcn_readfirstlane(tid / 64);  // rows CROWS*h ..
     // Register operands.  Every load is issued unconditionally (indices
     // clamped into the table) and the slots that do not apply are replaced
@@ -766,13 +788,19 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
 #pragma unroll
         for (int u = 0; u < DPT; ++u) {
             const int idx = tid + CTH * u;
-            const int qq = min(idx / T, nJ - 1), c = min(idx % T, nJ - 1);
+            int qq = idx / T, c = idx % T;
+            if constexpr (BLK) {
+                qq = rr0 + 8 * u;
+                c = cc0;
+            }
+            qq = min(qq, nJ - 1);
+            c = min(c, nJ - 1);
             dv[u] = (double)m[(size_t)(col0 + qq) * n + col0 + c];
         }
 #pragma unroll
         for (int u = 0; u < DPT; ++u) {
             const int idx = tid + CTH * u;
-            const int qq = idx / T, c = idx % T;
+            const int qq = BLK ? rr0 + 8 * u : idx / T, c = BLK ? cc0 : idx % T;
             if (qq >= 1 && qq <= c && c < nJ) L.dj(qq, c) = fma(dv[u], scale, (double)(T + qq - 1));
         }
     }
@@ -788,7 +816,7 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
             const int idx = tid + CTH * u;
-            const int rr = idx / T, c = idx % T;
+            const int rr = BLK ? rr0 + 8 * u : idx / T, c = BLK ? cc0 : idx % T;
             if (c < nJ) {
                 const int64_t cost = m[(size_t)(row0 + rr) * n + k] +
                                      m[(size_t)(k + 1) * n + col0 + c] +
@@ -809,7 +837,10 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
             for (int e = 0; e < SPR; ++e) {
                 const size_t so = (size_t)min(sl + e, PT - 1) * T * T;
 #pragma unroll
-                for (int u = 0; u < CPT; ++u) v[e][u] = src[so + tid + CTH * u];
+                for (int u = 0; u < CPT; ++u) {
+                    if constexpr (BLK) v[e][u] = src[so + (rr0 + 8 * u) * T + cc0];
+                    else v[e][u] = src[so + tid + CTH * u];
+                }
             }
 #pragma unroll
             for (int e = 0; e < SPR; ++e)
@@ -820,7 +851,7 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
         const int idx = tid + CTH * u;
-        const int rr = idx / T, c = idx % T;
+        const int rr = BLK ? rr0 + 8 * u : idx / T, c = BLK ? cc0 : idx % T;
         if (c < nJ) {
             L.Xt[c][rr] = fma((double)(int64_t)(key[u] >> kbits), scale, (double)(T - 1));
             L.Ks[rr][c] = (int32_t)(key[u] & kmask);
@@ -874,7 +905,7 @@ __device__ __forceinline__ void close_tile(Lds &L, const TileChain *__restrict__
     }
 
     for (int idx = tid; idx < T * T; idx += CTH) {
-        const int rr = idx / T, c = idx % T;
+        const int rr = BLK ? rr0 + 8 * ((idx - tid) / CTH) : idx / T, c = BLK ? cc0 : idx % T;
         if (c < nJ) {
             const size_t o = (size_t)(row0 + rr) * n + col0 + c;
             m[o] = (int64_t)(L.Xt[c][rr] * inv_scale);
